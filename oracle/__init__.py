@@ -1,0 +1,179 @@
+"""FP64 CPU oracle for soft demapping and Monte-Carlo MI/GMI (test infrastructure).
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. It wraps ``liboracle.so`` (built from
+``oracle.c`` with gcc) through ctypes and shares nothing with the GPU library.
+
+The quantities follow the standard definitions of the mutual information of a
+uniform discrete input over real AWGN, the bit-wise generalised mutual
+information under bit-metric decoding, and per-bit log-likelihood ratios; the
+paper lists these only among its acronyms (MI, GMI, LLR, BMD, AIR, AWGN), so
+the readings R1-R6 stated at the top of ``oracle.c`` apply.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(verbose: bool = False) -> str:
+    """Compile ``oracle.c`` into ``liboracle.so`` (gcc, OpenMP, portable -O3)."""
+    cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", "-Wextra",
+           "-o", _LIB + ".tmp", _SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    dp = ctypes.POINTER(ctypes.c_double)
+    up = ctypes.POINTER(ctypes.c_uint32)
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.oracle_bits.argtypes = [up, ctypes.c_int, ctypes.c_int]
+    lib.oracle_bits.restype = ctypes.c_int
+    lib.oracle_es.argtypes = [dp, ctypes.c_int, ctypes.c_int]
+    lib.oracle_es.restype = ctypes.c_double
+    lib.oracle_sigma2.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double]
+    lib.oracle_sigma2.restype = ctypes.c_double
+    lib.oracle_eval.argtypes = [dp, up, ctypes.c_int, ctypes.c_int, dp, up, ctypes.c_int64,
+                                ctypes.c_double, dp, dp, dp, dp]
+    lib.oracle_eval.restype = ctypes.c_int
+    lib.oracle_sweep.argtypes = [dp, up, ctypes.c_int, ctypes.c_int, up, fp, dp, ctypes.c_int64,
+                                 dp, ctypes.c_int, dp, dp, dp, dp]
+    lib.oracle_sweep.restype = ctypes.c_int
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a, ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _const(X, labels):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    labels = np.ascontiguousarray(labels, dtype=np.uint32)
+    if X.ndim != 2 or labels.shape != (X.shape[0],):
+        raise OracleError("X must be M x D and labels length M")
+    return X, labels
+
+
+def bits(labels, M: int, D: int) -> int:
+    """m = log2 M, or -1 if the constellation shape or labelling is invalid."""
+    labels = np.ascontiguousarray(labels, dtype=np.uint32)
+    return _load().oracle_bits(_ptr(labels, ctypes.c_uint32), M, D)
+
+
+def es(X) -> float:
+    """Average symbol energy (1/M) sum_j |x_j|^2."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    return _load().oracle_es(_ptr(X, ctypes.c_double), X.shape[0], X.shape[1])
+
+
+def sigma2(X, snr_db: float) -> float:
+    """Noise variance per real dimension: Es / (D * 10^(snr_db/10))."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    return _load().oracle_sigma2(es(X), X.shape[1], float(snr_db))
+
+
+def evaluate(X, labels, Y, snr_db: float, tx=None, llr: bool = True, per_sample: bool = False):
+    """Demap the block Y (N x D) at one SNR.
+
+    Returns a dict with ``stats`` = [MI, GMI, SE_MI, SE_GMI] (bits; needs tx),
+    ``llr`` (N x m, nats) and, with per_sample, ``u`` and ``v`` (bits).
+    """
+    X, labels = _const(X, labels)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    M, D = X.shape
+    if Y.ndim != 2 or Y.shape[1] != D:
+        raise OracleError("Y must be N x D")
+    N = Y.shape[0]
+    m = bits(labels, M, D)
+    if m < 0:
+        raise OracleError("invalid constellation")
+    out = {}
+    txa = None if tx is None else np.ascontiguousarray(tx, dtype=np.uint32)
+    stats = np.full(4, np.nan) if txa is not None else None
+    L = np.empty((N, m)) if llr else None
+    u = np.empty(N) if (per_sample and txa is not None) else None
+    v = np.empty(N) if (per_sample and txa is not None) else None
+    rc = _load().oracle_eval(_ptr(X, ctypes.c_double), _ptr(labels, ctypes.c_uint32), M, D,
+                             _ptr(Y, ctypes.c_double), _ptr(txa, ctypes.c_uint32), N,
+                             float(snr_db), _ptr(stats, ctypes.c_double), _ptr(L, ctypes.c_double),
+                             _ptr(u, ctypes.c_double), _ptr(v, ctypes.c_double))
+    if rc != 0:
+        raise OracleError(f"oracle_eval failed with code {rc}")
+    if stats is not None:
+        out["stats"] = stats
+    if L is not None:
+        out["llr"] = L
+    if u is not None:
+        out["u"], out["v"] = u, v
+    return out
+
+
+def sweep(X, labels, tx, Z, snr_db, llr: bool = True, per_sample: bool = False):
+    """SNR sweep with y = x_t + sigma_s z in FP64 from the caller's noise Z.
+
+    Z may be float32 (promoted exactly) or float64. Returns ``stats`` (S x 4),
+    ``llr`` (S x N x m) and, with per_sample, ``u`` and ``v`` (S x N).
+    """
+    X, labels = _const(X, labels)
+    M, D = X.shape
+    txa = np.ascontiguousarray(tx, dtype=np.uint32)
+    Z = np.asarray(Z)
+    if Z.ndim != 2 or Z.shape[1] != D or Z.shape[0] != txa.shape[0]:
+        raise OracleError("Z must be N x D with N = len(tx)")
+    z32 = np.ascontiguousarray(Z) if Z.dtype == np.float32 else None
+    z64 = None if z32 is not None else np.ascontiguousarray(Z, dtype=np.float64)
+    snr = np.ascontiguousarray(np.atleast_1d(snr_db), dtype=np.float64)
+    S, N = snr.shape[0], txa.shape[0]
+    m = bits(labels, M, D)
+    if m < 0:
+        raise OracleError("invalid constellation")
+    stats = np.full((S, 4), np.nan)
+    L = np.empty((S, N, m)) if llr else None
+    u = np.empty((S, N)) if per_sample else None
+    v = np.empty((S, N)) if per_sample else None
+    rc = _load().oracle_sweep(_ptr(X, ctypes.c_double), _ptr(labels, ctypes.c_uint32), M, D,
+                              _ptr(txa, ctypes.c_uint32), _ptr(z32, ctypes.c_float),
+                              _ptr(z64, ctypes.c_double), N, _ptr(snr, ctypes.c_double), S,
+                              _ptr(stats, ctypes.c_double), _ptr(L, ctypes.c_double),
+                              _ptr(u, ctypes.c_double), _ptr(v, ctypes.c_double))
+    if rc != 0:
+        raise OracleError(f"oracle_sweep failed with code {rc}")
+    out = {"stats": stats}
+    if L is not None:
+        out["llr"] = L
+    if u is not None:
+        out["u"], out["v"] = u, v
+    return out
+
+
+def threads() -> int:
+    """OpenMP threads the oracle library uses."""
+    return _load().oracle_threads()

@@ -1,0 +1,290 @@
+/*
+ * oracle.c -- plain FP64 CPU oracle for soft demapping and Monte-Carlo
+ * achievable-information-rate estimation (MI, and bit-wise GMI under
+ * bit-metric decoding) of an M-point, D-dimensional constellation over a
+ * real AWGN channel.
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library. It shares no code,
+ * header, table or constant with the GPU library; it is slow on purpose and
+ * follows the textbook definitions step by step so that it can be checked
+ * against the mathematics by eye.
+ *
+ * The paper names the quantities computed here only in its list of acronyms
+ * (achievable information rate, mutual information, generalised mutual
+ * information, log-likelihood ratio, bit-metric decoding, additive white
+ * Gaussian noise, signal-to-noise ratio). It prints no formula for them, so
+ * the definitions below are the standard ones, with these readings:
+ *
+ *  R1 SNR:    snr = 10^(SNR_dB/10) = Es / (D * sigma^2), where sigma^2 is the
+ *             noise variance per real dimension and Es = (1/M) sum_j |x_j|^2
+ *             is the average symbol energy under the uniform prior.
+ *  R2 prior:  the M points are equiprobable; with a bijective labelling the
+ *             m = log2 M bits are then uniform and independent.
+ *  R3 LLR:    L_k = ln P(b_k = 0 | y) - ln P(b_k = 1 | y), in nats.
+ *  R4 bits:   bit k of label l is (l >> k) & 1; LLR column k is bit k.
+ *  R5 MC:     the estimators use the known transmitted index t_n:
+ *               u_n = log2 sum_j p(y_n|x_j) - log2 p(y_n|x_t)        (>= 0)
+ *               v_n = sum_k [log2 sum_j p(y_n|x_j)
+ *                            - log2 sum_{j: b_k(j)=b_k(t)} p(y_n|x_j)] (>= 0)
+ *               MI  = log2 M - mean(u),  GMI = m - mean(v)
+ *             and SE = sample standard deviation / sqrt(N). No clamping.
+ *  R6 sweep:  y_n = x_{t_n} + sigma_s z_n, formed in FP64 from the caller's
+ *             unit-variance noise z_n, the same (t, z) at every SNR point.
+ *
+ * Every log-sum-exp is exact up to FP64 rounding at any SNR: a common shift
+ * (the global maximum) is used for a bit side only when that side's sum is
+ * far inside the FP64 range; otherwise the side is recomputed with its own
+ * maximum as shift.
+ *
+ * Sums over samples use Neumaier compensated summation inside fixed chunks
+ * of ORACLE_CHUNK samples, and the chunk results are added in chunk order,
+ * so the result does not depend on the number of OpenMP threads.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_CHUNK 1024
+#define ORACLE_MAX_M 4096
+#define ORACLE_MAX_D 64
+
+enum { ORACLE_OK = 0, ORACLE_E_INVAL = -1, ORACLE_E_NOMEM = -3 };
+
+/* ---- Neumaier (improved Kahan) summation ------------------------------ */
+typedef struct { double s, c; } nsum_t;
+
+static void nsum_add(nsum_t *a, double x) {
+  double t = a->s + x;
+  if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+  else a->c += (x - t) + a->s;
+  a->s = t;
+}
+static double nsum_val(const nsum_t *a) { return a->s + a->c; }
+
+/* ---- constellation checks (R2, R4) ------------------------------------ */
+/* Returns m = log2 M, or -1 if M is not a power of two in [2, 4096], D is
+ * outside [1, 64], or the labels are not a bijection onto {0..M-1}. */
+int oracle_bits(const uint32_t *labels, int M, int D) {
+  if (M < 2 || M > ORACLE_MAX_M || (M & (M - 1)) != 0) return -1;
+  if (D < 1 || D > ORACLE_MAX_D || labels == NULL) return -1;
+  int m = 0;
+  while ((1 << m) < M) ++m;
+  char *seen = (char *)calloc((size_t)M, 1);
+  if (!seen) return -1;
+  for (int j = 0; j < M; ++j) {
+    if (labels[j] >= (uint32_t)M || seen[labels[j]]) { free(seen); return -1; }
+    seen[labels[j]] = 1;
+  }
+  free(seen);
+  return m;
+}
+
+/* Average symbol energy Es = (1/M) sum_j sum_d X[j][d]^2 (R1). */
+double oracle_es(const double *X, int M, int D) {
+  nsum_t acc = {0.0, 0.0};
+  for (int j = 0; j < M; ++j)
+    for (int d = 0; d < D; ++d) nsum_add(&acc, X[(size_t)j * D + d] * X[(size_t)j * D + d]);
+  return nsum_val(&acc) / (double)M;
+}
+
+/* Noise variance per real dimension for a given SNR in dB (R1). */
+double oracle_sigma2(double es, int D, double snr_db) {
+  return es / ((double)D * pow(10.0, snr_db / 10.0));
+}
+
+/* ---- one received sample ---------------------------------------------- */
+/* log-sum-exp over the points j with ((labels[j] >> k) & 1) == b, shifted by
+ * that side's own maximum; a[] holds the natural-log metrics. */
+static double side_lse_own_shift(const double *a, const uint32_t *labels, int M, int k, int b) {
+  double amax = -INFINITY;
+  for (int j = 0; j < M; ++j)
+    if ((int)((labels[j] >> k) & 1u) == b && a[j] > amax) amax = a[j];
+  double s = 0.0;
+  for (int j = 0; j < M; ++j)
+    if ((int)((labels[j] >> k) & 1u) == b) s += exp(a[j] - amax);
+  return amax + log(s);
+}
+
+/* Per-sample demapping of y (length D). Writes the m LLRs (nats) to llr if
+ * non-NULL, and, if t >= 0, the MI and GMI terms u and v (bits).
+ * a, side are scratch arrays of length M and 2*m. */
+static void demap_one(const double *X, const uint32_t *labels, int M, int D, int m,
+                      const double *y, double sigma2, int64_t t,
+                      double *a, double *side, double *llr, double *u, double *v) {
+  const double inv2s2 = 1.0 / (2.0 * sigma2);
+  /* a_j = ln p(y|x_j) up to a constant common to all j:
+   *       a_j = -|y - x_j|^2 / (2 sigma^2), direct differences. */
+  double amax = -INFINITY;
+  for (int j = 0; j < M; ++j) {
+    double d2 = 0.0;
+    for (int d = 0; d < D; ++d) {
+      double diff = y[d] - X[(size_t)j * D + d];
+      d2 += diff * diff;
+    }
+    a[j] = -d2 * inv2s2;
+    if (a[j] > amax) amax = a[j];
+  }
+  /* Total log-sum-exp with the global maximum as shift. */
+  double stot = 0.0;
+  for (int k = 0; k < 2 * m; ++k) side[k] = 0.0;
+  for (int j = 0; j < M; ++j) {
+    double e = exp(a[j] - amax);
+    stot += e;
+    for (int k = 0; k < m; ++k) side[2 * k + ((labels[j] >> k) & 1u)] += e;
+  }
+  const double lse = amax + log(stot);
+  /* Per bit side: the shared shift is exact while the side sum is far inside
+   * the FP64 range (every dropped term is then below 1e-250 / 2^52 of it);
+   * otherwise use the side's own maximum. */
+  double lse_side[2 * 12];
+  for (int k = 0; k < m; ++k)
+    for (int b = 0; b < 2; ++b) {
+      double s = side[2 * k + b];
+      lse_side[2 * k + b] = (s > 1e-250) ? amax + log(s)
+                                         : side_lse_own_shift(a, labels, M, k, b);
+    }
+  if (llr)
+    for (int k = 0; k < m; ++k) llr[k] = lse_side[2 * k + 0] - lse_side[2 * k + 1];
+  if (t >= 0) {
+    const double ln2 = log(2.0);
+    *u = (lse - a[t]) / ln2;
+    double acc = 0.0;
+    for (int k = 0; k < m; ++k) {
+      int bt = (int)((labels[t] >> k) & 1u);
+      acc += (lse - lse_side[2 * k + bt]) / ln2;
+    }
+    *v = acc;
+  }
+}
+
+/* ---- statistics -------------------------------------------------------- */
+/* MI = log2 M - mean(u), GMI = m - mean(v), SE = sd/sqrt(N) with the sample
+ * standard deviation (N-1 denominator); SE is NaN for N = 1. Sums are
+ * chunked Neumaier sums; the deviation uses a second pass about the mean. */
+static double chunked_sum(const double *x, int64_t N, double shift, int square) {
+  int64_t nchunks = (N + ORACLE_CHUNK - 1) / ORACLE_CHUNK;
+  nsum_t total = {0.0, 0.0};
+  for (int64_t c = 0; c < nchunks; ++c) {
+    nsum_t part = {0.0, 0.0};
+    int64_t hi = (c + 1) * ORACLE_CHUNK < N ? (c + 1) * ORACLE_CHUNK : N;
+    for (int64_t n = c * ORACLE_CHUNK; n < hi; ++n) {
+      double d = x[n] - shift;
+      nsum_add(&part, square ? d * d : d);
+    }
+    nsum_add(&total, nsum_val(&part));
+  }
+  return nsum_val(&total);
+}
+
+static void fill_stats(const double *u, const double *v, int64_t N, int M, int m, double *stats) {
+  double mu = chunked_sum(u, N, 0.0, 0) / (double)N;
+  double mv = chunked_sum(v, N, 0.0, 0) / (double)N;
+  stats[0] = log2((double)M) - mu;
+  stats[1] = (double)m - mv;
+  if (N > 1) {
+    double su = chunked_sum(u, N, mu, 1) / (double)(N - 1);
+    double sv = chunked_sum(v, N, mv, 1) / (double)(N - 1);
+    stats[2] = sqrt(su / (double)N);
+    stats[3] = sqrt(sv / (double)N);
+  } else {
+    stats[2] = NAN;
+    stats[3] = NAN;
+  }
+}
+
+/* ---- public entry points --------------------------------------------- */
+/* Demap a given received block Y (N x D, row-major, FP64) at one SNR.
+ *  tx:    transmitted indices (N) into X, or NULL (then no MI/GMI terms).
+ *  stats: [4] = MI, GMI, SE_MI, SE_GMI (bits per D-dim symbol); needs tx.
+ *  llr:   N x m LLRs in nats, or NULL.
+ *  u, v:  per-sample MI/GMI terms (N each), or NULL.
+ * Returns 0, or a negative error code for invalid arguments or no memory. */
+int oracle_eval(const double *X, const uint32_t *labels, int M, int D,
+                const double *Y, const uint32_t *tx, int64_t N, double snr_db,
+                double *stats, double *llr, double *u, double *v) {
+  int m = oracle_bits(labels, M, D);
+  if (m < 0 || X == NULL || Y == NULL || N < 1) return ORACLE_E_INVAL;
+  if ((stats || u || v) && tx == NULL) return ORACLE_E_INVAL;
+  if (tx)
+    for (int64_t n = 0; n < N; ++n)
+      if (tx[n] >= (uint32_t)M) return ORACLE_E_INVAL;
+  const double sigma2 = oracle_sigma2(oracle_es(X, M, D), D, snr_db);
+  double *uu = u, *vv = v, *own = NULL;
+  if (tx && (!u || !v)) {
+    own = (double *)malloc(sizeof(double) * 2 * (size_t)N);
+    if (!own) return ORACLE_E_NOMEM;
+    uu = u ? u : own;
+    vv = v ? v : own + N;
+  }
+  int fail = 0;
+#pragma omp parallel
+  {
+    double *a = (double *)malloc(sizeof(double) * (size_t)M);
+    double side[2 * 12];
+    if (!a) {
+#pragma omp atomic write
+      fail = 1;
+    } else {
+#pragma omp for schedule(static)
+      for (int64_t n = 0; n < N; ++n) {
+        double du = 0.0, dv = 0.0;
+        demap_one(X, labels, M, D, m, Y + (size_t)n * D, sigma2, tx ? (int64_t)tx[n] : -1,
+                  a, side, llr ? llr + (size_t)n * m : NULL, &du, &dv);
+        if (tx) { uu[n] = du; vv[n] = dv; }
+      }
+    }
+    free(a);
+  }
+  if (!fail && stats) fill_stats(uu, vv, N, M, m, stats);
+  free(own);
+  return fail ? ORACLE_E_NOMEM : ORACLE_OK;
+}
+
+/* SNR sweep from unit noise (R6): for each of the S SNR points,
+ * y_n = X[tx_n] + sigma_s * Z_n in FP64 from the FP32 noise Z (N x D), then
+ * demap as oracle_eval. stats is S x 4, llr S x N x m, u and v S x N;
+ * each may be NULL. Z64 may replace Z with FP64 noise (then Z is unused). */
+int oracle_sweep(const double *X, const uint32_t *labels, int M, int D,
+                 const uint32_t *tx, const float *Z, const double *Z64, int64_t N,
+                 const double *snr_db, int S,
+                 double *stats, double *llr, double *u, double *v) {
+  int m = oracle_bits(labels, M, D);
+  if (m < 0 || X == NULL || tx == NULL || (Z == NULL && Z64 == NULL) || N < 1 ||
+      snr_db == NULL || S < 1)
+    return ORACLE_E_INVAL;
+  for (int64_t n = 0; n < N; ++n)
+    if (tx[n] >= (uint32_t)M) return ORACLE_E_INVAL;
+  const double es = oracle_es(X, M, D);
+  double *y = (double *)malloc(sizeof(double) * (size_t)N * D);
+  if (!y) return ORACLE_E_NOMEM;
+  int rc = ORACLE_OK;
+  for (int s = 0; s < S && rc == ORACLE_OK; ++s) {
+    const double sigma = sqrt(oracle_sigma2(es, D, snr_db[s]));
+    for (int64_t n = 0; n < N; ++n)
+      for (int d = 0; d < D; ++d) {
+        double z = Z64 ? Z64[(size_t)n * D + d] : (double)Z[(size_t)n * D + d];
+        y[(size_t)n * D + d] = X[(size_t)tx[n] * D + d] + sigma * z;
+      }
+    rc = oracle_eval(X, labels, M, D, y, tx, N, snr_db[s],
+                     stats ? stats + 4 * s : NULL,
+                     llr ? llr + (size_t)s * N * m : NULL,
+                     u ? u + (size_t)s * N : NULL,
+                     v ? v + (size_t)s * N : NULL);
+  }
+  free(y);
+  return rc;
+}
+
+/* Number of OpenMP threads the oracle runs with (1 without OpenMP). */
+int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -1,0 +1,289 @@
+"""Pins of the FP64 oracle against closed forms, identities, invariances and brute force.
+
+The paper defines none of these quantities beyond naming them (MI, GMI, LLR,
+BMD, AWGN in its acronym list), so the pins come from the mathematics:
+textbook capacities by quadrature, exact same-sample identities of product
+constellations, the LLR of binary antipodal signalling, limits, invariances,
+and an independent high-precision Bayes computation on tiny constellations.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute, truths
+from paper_2108_07001_amd import inputs
+
+LN2 = math.log(2.0)
+
+
+def _y(X, tx, z, snr_db):
+    """Received block x_t + sigma z for a check (sigma from the SNR reading R1)."""
+    es = np.mean(np.sum(X * X, axis=1))
+    sigma = math.sqrt(es / (X.shape[1] * 10 ** (snr_db / 10)))
+    return X[tx] + sigma * np.asarray(z, dtype=np.float64)
+
+
+# ---- constellation handling ------------------------------------------------
+
+def test_bits_validation():
+    assert oracle.bits(np.arange(16), 16, 4) == 4
+    assert oracle.bits(np.arange(2), 2, 1) == 1
+    assert oracle.bits(np.arange(4096), 4096, 12) == 12
+    assert oracle.bits(np.arange(12), 12, 4) == -1          # not a power of two
+    assert oracle.bits(np.array([0, 1, 1, 3]), 4, 2) == -1  # not a bijection
+    assert oracle.bits(np.array([0, 1, 2, 4]), 4, 2) == -1  # label out of range
+    assert oracle.bits(np.arange(4), 4, 0) == -1            # D out of range
+    assert oracle.bits(np.arange(1), 1, 2) == -1
+
+
+def test_es_and_sigma2_pmqpsk():
+    X, _ = inputs.pm_qpsk()
+    assert oracle.es(X) == pytest.approx(2.0, abs=1e-15)
+    # snr = Es / (D sigma^2): at 0 dB sigma^2 = 2 / 4
+    assert oracle.sigma2(X, 0.0) == pytest.approx(0.5, rel=1e-15)
+    assert oracle.sigma2(X, 10.0) == pytest.approx(0.05, rel=1e-14)
+
+
+# ---- textbook special cases (LLR of binary antipodal signalling) -----------
+
+@pytest.mark.parametrize("snr_db", [-10.0, 0.0, 10.0, 30.0, 45.0])
+def test_bpsk_llr_is_2y_over_sigma2(snr_db):
+    X = np.array([[1.0], [-1.0]])      # label 0 -> +1, label 1 -> -1
+    lab = np.array([0, 1], dtype=np.uint32)
+    rng = np.random.default_rng(7)
+    Y = rng.normal(0, 2.0, size=(500, 1))
+    Y[:3, 0] = [0.0, 3.0, -7.5]
+    out = oracle.evaluate(X, lab, Y, snr_db)
+    s2 = 1.0 / 10 ** (snr_db / 10)
+    ref = 2.0 * Y[:, 0] / s2
+    # |L| reaches ~5e5 nats at 45 dB: the own-shift path of starved sides
+    np.testing.assert_allclose(out["llr"][:, 0], ref, rtol=1e-12, atol=1e-12)
+
+
+def test_any_two_point_set():
+    rng = np.random.default_rng(11)
+    X = rng.normal(size=(2, 5))
+    lab = np.array([1, 0], dtype=np.uint32)          # point 0 carries bit 1
+    Y = rng.normal(size=(300, 5)) * 1.5
+    snr_db = 6.0
+    s2 = oracle.sigma2(X, snr_db)
+    out = oracle.evaluate(X, lab, Y, snr_db)
+    d0 = np.sum((Y - X[1]) ** 2, axis=1)             # bit 0 <-> point 1
+    d1 = np.sum((Y - X[0]) ** 2, axis=1)
+    np.testing.assert_allclose(out["llr"][:, 0], (d1 - d0) / (2 * s2), rtol=1e-12, atol=1e-11)
+
+
+# ---- PM-QPSK: same-sample identities and the closed-form capacity ----------
+
+def test_pmqpsk_llr_identity_and_mi_equals_gmi():
+    w = inputs.make("pmqpsk", N=4000)
+    r = oracle.sweep(w.X, w.labels, w.tx, w.z, w.snr_db, per_sample=True)
+    for i, s in enumerate(w.snr_db):
+        s2 = oracle.sigma2(w.X, s)
+        Y = _y(w.X, w.tx, w.z, s)
+        # bit d of the label is the sign of coordinate d: L_d = sqrt(2) y_d / sigma^2
+        np.testing.assert_allclose(r["llr"][i], math.sqrt(2.0) * Y / s2, rtol=1e-11, atol=1e-10)
+        # the likelihood factorises over the coordinates: MI term == GMI term
+        np.testing.assert_allclose(r["u"][i], r["v"][i], rtol=1e-12, atol=1e-12)
+
+
+def test_bpsk_capacity_quadrature_agrees():
+    for s_db in [-2.0, 0.0, 5.0, 10.0, 15.0]:
+        s = 10 ** (s_db / 10)
+        assert truths.c_bpsk(s) == pytest.approx(truths.c_bpsk_gauss_hermite(s), abs=1e-8)
+    # first-order low-SNR slope of any zero-mean binary input: s / (2 ln 2) bits
+    s = 1e-4
+    assert truths.c_bpsk(s) == pytest.approx(s / (2 * LN2), rel=1e-3)
+    assert truths.c_bpsk(1e3) == pytest.approx(1.0, abs=1e-12)
+
+
+def test_pmqpsk_mi_matches_capacity():
+    w = inputs.make("pmqpsk")          # full N = 1e5
+    r = oracle.sweep(w.X, w.labels, w.tx, w.z, w.snr_db, llr=False)
+    for i, s_db in enumerate(w.snr_db):
+        truth = 4.0 * truths.c_bpsk(10 ** (s_db / 10))
+        mi, gmi, se_mi, se_gmi = r["stats"][i]
+        # where the rate deficit is carried by events rarer than ~1/N the sample
+        # SE cannot see it; there the estimate must only lie between truth-ish and 4
+        slack = 1e-9 if (4.0 - truth) * w.N > 50 else (4.0 - truth) + 1e-9
+        assert abs(mi - truth) <= 4 * se_mi + slack, (s_db, mi, truth, se_mi)
+        assert abs(gmi - truth) <= 4 * se_gmi + slack
+        assert mi <= 4.0 + 1e-12
+        assert abs(mi - gmi) < 1e-12
+
+
+def test_gray_qpsk_two_dims_is_twice_bpsk():
+    X = np.array([[1, 1], [-1, 1], [1, -1], [-1, -1]], dtype=float) / math.sqrt(2)
+    lab = np.arange(4, dtype=np.uint32)
+    tx, z = inputs.random_block(5, 4, 50_000, 2, f64=True)
+    r = oracle.sweep(X, lab, tx, z, [3.0])
+    truth = 2.0 * truths.c_bpsk(10 ** 0.3)
+    mi, gmi, se_mi, _ = r["stats"][0]
+    assert abs(mi - truth) <= 4 * se_mi
+    assert abs(mi - gmi) < 1e-12
+
+
+# ---- limits -------------------------------------------------------------------
+
+def test_high_snr_limit_is_log2_m():
+    X, lab = inputs.random_constellation(3, 32, 4)
+    tx, z = inputs.random_block(4, 32, 2000, 4)
+    r = oracle.sweep(X, lab, tx, z, [60.0, 80.0])
+    np.testing.assert_allclose(r["stats"][:, 0], 5.0, atol=1e-12)
+    np.testing.assert_allclose(r["stats"][:, 1], 5.0, atol=1e-12)
+
+
+def test_low_snr_limit_is_zero():
+    X, lab = inputs.random_constellation(3, 16, 2)
+    tx, z = inputs.random_block(9, 16, 20_000, 2)
+    r = oracle.sweep(X, lab, tx, z, [-40.0])
+    mi, gmi, se_mi, se_gmi = r["stats"][0]
+    # first-order slope: tr Cov(X) / (2 sigma^2 ln 2) bits
+    s2 = oracle.sigma2(X, -40.0)
+    slope = np.trace(np.cov(X.T, bias=True)) / (2 * s2 * LN2)
+    assert abs(mi - slope) <= 4 * se_mi + 1e-7
+    assert abs(gmi) <= 4 * se_gmi + 1e-5
+
+
+# ---- product constellation (8-PSK x 8-PSK) --------------------------------
+
+def test_psk8x8_mi_is_sum_of_polarisations():
+    w = inputs.make("psk8x8", N=3000)
+    th = 2 * math.pi * np.arange(8) / 8
+    P = np.stack([np.cos(th), np.sin(th)], axis=1) / math.sqrt(2.0)
+    lab8 = np.arange(8, dtype=np.uint32)
+    tx_x, tx_y = w.tx // 8, w.tx % 8
+    for s_db in [-2.0, 6.0, 14.0]:
+        Y = _y(w.X, w.tx, w.z, s_db)
+        full = oracle.evaluate(w.X, w.labels, Y, s_db, tx=w.tx, per_sample=True, llr=False)
+        # each polarisation is 8-PSK with half the energy over half the dimensions:
+        # the same per-dimension noise variance, hence the same SNR in dB
+        xp = oracle.evaluate(P, lab8, Y[:, :2], s_db, tx=tx_x, per_sample=True, llr=False)
+        yp = oracle.evaluate(P, lab8, Y[:, 2:], s_db, tx=tx_y, per_sample=True, llr=False)
+        np.testing.assert_allclose(full["u"], xp["u"] + yp["u"], rtol=1e-11, atol=1e-11)
+
+
+def test_psk8x8_mi_matches_quadrature():
+    w = inputs.make("psk8x8", N=40_000)
+    snrs = [0.0, 8.0, 14.0]
+    r = oracle.sweep(w.X, w.labels, w.tx, w.z, snrs, llr=False)
+    for i, s_db in enumerate(snrs):
+        truth = 2.0 * truths.mi_8psk(10 ** (s_db / 10))
+        mi, _, se, _ = r["stats"][i]
+        assert abs(mi - truth) <= 4 * se + 2e-6, (s_db, mi, truth, se)
+
+
+# ---- invariances -------------------------------------------------------------
+
+def _case(seed=21, M=16, D=3, N=1500, snr=7.0):
+    X, lab = inputs.random_constellation(seed, M, D)
+    tx, z = inputs.random_block(seed + 1, M, N, D, f64=True)
+    return X, lab, tx, z, snr
+
+
+def test_joint_permutation_of_points_and_labels():
+    X, lab, tx, z, snr = _case()
+    base = oracle.sweep(X, lab, tx, z, [snr], per_sample=True)
+    p = np.random.default_rng(1).permutation(X.shape[0])
+    inv = np.argsort(p)
+    moved = oracle.sweep(X[p], lab[p], inv[tx].astype(np.uint32), z, [snr], per_sample=True)
+    np.testing.assert_allclose(moved["llr"], base["llr"], rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(moved["u"], base["u"], rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(moved["v"], base["v"], rtol=1e-10, atol=1e-12)
+
+
+def test_rotation_and_scaling():
+    X, lab, tx, z, snr = _case()
+    base = oracle.sweep(X, lab, tx, z, [snr], per_sample=True)
+    Q, _ = np.linalg.qr(np.random.default_rng(2).normal(size=(3, 3)))
+    # rotate points and noise together: the received block rotates with them
+    rot = oracle.sweep(X @ Q.T, lab, tx, z @ Q.T, [snr], per_sample=True)
+    np.testing.assert_allclose(rot["llr"], base["llr"], rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(rot["u"], base["u"], rtol=1e-9, atol=1e-11)
+    # scaling the points at a fixed SNR in dB scales sigma with them (R1)
+    sc = oracle.sweep(3.7 * X, lab, tx, z, [snr], per_sample=True)
+    np.testing.assert_allclose(sc["llr"], base["llr"], rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(sc["v"], base["v"], rtol=1e-10, atol=1e-12)
+
+
+def test_label_complement_and_bit_permutation():
+    X, lab, tx, z, snr = _case()
+    base = oracle.sweep(X, lab, tx, z, [snr], per_sample=True)
+    flip = oracle.sweep(X, lab ^ np.uint32(0b0100), tx, z, [snr], per_sample=True)
+    np.testing.assert_allclose(flip["llr"][0][:, 2], -base["llr"][0][:, 2], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(flip["llr"][0][:, [0, 1, 3]], base["llr"][0][:, [0, 1, 3]], rtol=1e-12)
+    np.testing.assert_allclose(flip["v"], base["v"], rtol=1e-12, atol=1e-12)
+    # relabel by a permutation of bit positions: LLR columns permute the same way
+    perm = [2, 0, 3, 1]          # new bit perm[k] <- old bit k
+    lab2 = np.zeros_like(lab)
+    for k in range(4):
+        lab2 |= ((lab >> k) & 1) << perm[k]
+    pb = oracle.sweep(X, lab2, tx, z, [snr], per_sample=True)
+    for k in range(4):
+        np.testing.assert_allclose(pb["llr"][0][:, perm[k]], base["llr"][0][:, k], rtol=1e-12, atol=1e-12)
+    # the MI does not depend on the labels at all
+    other = oracle.sweep(X, np.random.default_rng(5).permutation(16).astype(np.uint32), tx, z,
+                         [snr], per_sample=True)
+    np.testing.assert_allclose(other["u"], base["u"], rtol=1e-12, atol=1e-12)
+
+
+# ---- bounds and internal identities --------------------------------------
+
+def test_per_sample_terms_nonnegative_and_gmi_identity():
+    X, lab, tx, z, _ = _case(N=4000)
+    r = oracle.sweep(X, lab, tx, z, [-3.0, 5.0, 15.0, 30.0], per_sample=True)
+    assert (r["u"] >= -1e-12).all() and (r["v"] >= -1e-12).all()
+    # v = sum_k log2(1 + exp(-(1 - 2 b_k) L_k)) with b_k the transmitted bit
+    b = ((lab[tx][:, None] >> np.arange(4)) & 1).astype(float)
+    for i in range(4):
+        x = -(1 - 2 * b) * r["llr"][i]
+        ref = np.sum(np.logaddexp(0.0, x), axis=1) / LN2
+        np.testing.assert_allclose(r["v"][i], ref, rtol=1e-10, atol=1e-10)
+    # GMI <= MI for the true values; same-sample estimates within a few SE
+    for mi, gmi, se_mi, se_gmi in r["stats"]:
+        assert gmi - mi <= 4 * max(se_mi, se_gmi) + 1e-12
+
+
+def test_standard_errors_are_sample_sd_over_sqrt_n():
+    X, lab, tx, z, snr = _case(N=3000)
+    r = oracle.sweep(X, lab, tx, z, [snr], per_sample=True)
+    mi, gmi, se_mi, se_gmi = r["stats"][0]
+    assert mi == pytest.approx(4 - np.mean(r["u"][0]), abs=1e-13)
+    assert gmi == pytest.approx(4 - np.mean(r["v"][0]), abs=1e-13)
+    assert se_mi == pytest.approx(np.std(r["u"][0], ddof=1) / math.sqrt(3000), rel=1e-10)
+    assert se_gmi == pytest.approx(np.std(r["v"][0], ddof=1) / math.sqrt(3000), rel=1e-10)
+
+
+def test_sweep_equals_eval_on_formed_block():
+    X, lab, tx, z, snr = _case()
+    sw = oracle.sweep(X, lab, tx, z, [snr], per_sample=True)
+    ev = oracle.evaluate(X, lab, _y(X, tx, z, snr), snr, tx=tx, per_sample=True)
+    np.testing.assert_allclose(sw["llr"][0], ev["llr"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(sw["u"][0], ev["u"], rtol=1e-12, atol=1e-14)
+
+
+# ---- brute force (mpmath Bayes) ---------------------------------------------
+
+@pytest.mark.parametrize("M,D,snr", [(2, 1, 3.0), (4, 2, 0.0), (8, 3, 9.0), (8, 2, 26.0), (16, 4, 12.0)])
+def test_brute_force_agrees(M, D, snr):
+    X, lab = inputs.random_constellation(100 + M + D, M, D)
+    tx, z = inputs.random_block(200 + M, M, 60, D, f64=True)
+    Y = _y(X, tx, z, snr)
+    Y[0] += 5.0                       # one sample far from every point
+    o = oracle.evaluate(X, lab, Y, snr, tx=tx, per_sample=True)
+    b = brute.demap(X, lab, Y, snr, tx=tx)
+    np.testing.assert_allclose(o["llr"], b["llr"], rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(o["u"], b["u"], rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(o["v"], b["v"], rtol=1e-10, atol=1e-10)
+    assert o["stats"][0] == pytest.approx(b["mi"], abs=1e-10)
+    assert o["stats"][1] == pytest.approx(b["gmi"], abs=1e-10)
+
+
+def test_rejects_bad_arguments():
+    X, lab = inputs.pm_qpsk()
+    with pytest.raises(oracle.OracleError):
+        oracle.evaluate(X, lab, np.zeros((3, 4)), 0.0, tx=np.array([0, 16, 1], dtype=np.uint32))
+    with pytest.raises(oracle.OracleError):
+        oracle.evaluate(X, np.zeros(16, dtype=np.uint32), np.zeros((3, 4)), 0.0)
