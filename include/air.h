@@ -1,0 +1,149 @@
+/*
+ * air.h -- C ABI of libair: soft demapping (per-bit LLRs) and Monte-Carlo
+ * achievable-information-rate estimation (MI, and bit-wise GMI under
+ * bit-metric decoding) of D-dimensional constellations over real AWGN, on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * The paper (a software-defined GPU receiver) only names these quantities in
+ * its list of acronyms -- achievable information rate, mutual information,
+ * generalised mutual information, log-likelihood ratio, bit-metric decoding,
+ * additive white Gaussian noise, signal-to-noise ratio -- and its receiver
+ * demaps the hard decisions of its adaptive equaliser (Section II). The
+ * definitions used here are the standard ones, with these readings:
+ *
+ *  - SNR:   snr = 10^(snr_db/10) = Es / (D sigma^2); sigma^2 is the noise
+ *           variance per real dimension, Es = (1/M) sum_j |x_j|^2 the average
+ *           energy of the constellation under a uniform prior.
+ *  - LLR:   L_k = ln P(b_k=0 | y) - ln P(b_k=1 | y), natural log (nats).
+ *  - Bits:  bit k of a label l is (l >> k) & 1; LLR column k is bit k.
+ *  - MI:    log2 M - mean_n log2( sum_j p(y_n|x_j) / p(y_n|x_{t_n}) )
+ *  - GMI:   m - mean_n sum_k log2( sum_j p(y_n|x_j)
+ *                                / sum_{j: b_k(j) = b_k(t_n)} p(y_n|x_j) )
+ *           with m = log2 M. Both in bits per D-dimensional symbol, with
+ *           standard errors sd/sqrt(N) (sample standard deviation). No clamping.
+ *  - Sweep: y_n = x_{t_n} + sigma_s z_n from the caller's unit-variance noise
+ *           z_n; the same (t, z) is used at every SNR point.
+ *
+ * Conventions for every call:
+ *  - Every function returns an air_status and never throws across the ABI.
+ *    On failure air_last_error() describes the cause.
+ *  - Pointers named *_dev are device memory owned by the caller (for example
+ *    the storage of a torch tensor on the context's device); pointers named
+ *    *_host are host memory. Layouts are dense and row-major.
+ *  - Work is enqueued asynchronously on the context's HIP stream; results in
+ *    device buffers are valid once the stream has reached that point
+ *    (air_sync, or any later operation on the same stream).
+ *  - A context is not thread-safe; use one per host thread.
+ *  - The constellation X is given in FP64 on the host and kept on the device.
+ *    Transmitted indices tx index the rows of X (not labels).
+ */
+#ifndef LIBAIR_AIR_H
+#define LIBAIR_AIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct air_ctx air_ctx;
+typedef struct air_const air_const;
+
+typedef enum {
+  AIR_OK = 0,
+  AIR_E_INVAL = -1,        /* invalid argument (null pointer, bad size, bad labels...) */
+  AIR_E_UNSUPPORTED = -2,  /* valid request this build or precision cannot serve        */
+  AIR_E_NOMEM = -3,        /* device or host allocation failed                          */
+  AIR_E_DEVICE = -4,       /* a HIP runtime call failed                                 */
+  AIR_E_BUSY = -5,         /* resource temporarily unavailable                          */
+  AIR_E_RANGE = -6         /* device data out of range (a tx index >= M was seen)       */
+} air_status;
+
+/* Arithmetic of the demapping kernels.
+ *  AIR_FP64    FP64 throughout (distances, log-sum-exp, sums). Y / Z / LLR are double.
+ *  AIR_FP32    FP32 vector ALU, squared distances by direct differences.
+ *  AIR_BF16X3  exponent tile on the matrix cores from bfloat16 hi+lo splits
+ *              (three products per term) with FP32 accumulation; FP32 log-sum-exp.
+ *  AIR_FP16X3  as AIR_BF16X3 with half-precision hi+lo splits.
+ * Except AIR_FP64, Y / Z are float and LLRs float. Sums over samples are
+ * always FP64. Every FP32-family result that is not representable within the
+ * stated accuracy by the fast path (very large |LLR|, a received point far
+ * from every constellation point) is recomputed exactly in FP32. */
+typedef enum {
+  AIR_FP64 = 0,
+  AIR_FP32 = 1,
+  AIR_BF16X3 = 2,
+  AIR_FP16X3 = 3
+} air_prec;
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t; NULL = the default stream). *out receives the context. */
+air_status air_create(air_ctx **out, int device, void *hip_stream);
+
+/* Release a context and its workspace (synchronises its stream first). NULL is ignored. */
+void air_destroy(air_ctx *ctx);
+
+/* Issue subsequent work on another stream of the same device. */
+air_status air_set_stream(air_ctx *ctx, void *hip_stream);
+
+/* Message describing the last failure on this context ("" if none). Owned by the context. */
+const char *air_last_error(const air_ctx *ctx);
+
+/* Wait for all work issued on the context's stream. Returns AIR_E_RANGE (and
+ * clears the flag) if a kernel saw a transmitted index >= M since the last
+ * air_sync; the statistics of the affected calls are then NaN. */
+air_status air_sync(air_ctx *ctx);
+
+/* Upload a constellation.
+ *  X_host:      M x D FP64 points, row-major.
+ *  labels_host: M bit labels, a bijection onto {0, ..., M-1}.
+ *  M = 2^m with 2 <= M <= 4096; 1 <= D <= 16.
+ * The handle owns device copies in every layout the kernels use (label order,
+ * FP64 / FP32 coordinates, split half / bfloat16 operands). It lives on the
+ * context's device and may only be used with the context that created it. */
+air_status air_const_create(air_ctx *ctx, const double *X_host, const uint32_t *labels_host,
+                            int M, int D, air_const **out);
+
+/* Release a constellation (waits for device work that may still read it). NULL is ignored.
+ * May be called after its context was destroyed. */
+void air_const_destroy(air_const *c);
+
+/* Bits per label, m = log2 M, of a constellation (0 if c is NULL). */
+int air_const_bits(const air_const *c);
+
+/* Soft demapping of a received block at one SNR.
+ *  Y_dev:   N x D received points (double for AIR_FP64, else float).
+ *  llr_dev: N x m LLRs in nats (double for AIR_FP64, else float).
+ * N >= 1. */
+air_status air_llr(air_ctx *ctx, const air_const *c, const void *Y_dev, int64_t N,
+                   double snr_db, air_prec prec, void *llr_dev);
+
+/* Monte-Carlo MI and GMI of a received block at one SNR, with known
+ * transmitted indices.
+ *  Y_dev:     N x D received points (double for AIR_FP64, else float).
+ *  tx_dev:    N transmitted indices into the rows of X (uint32).
+ *  stats_dev: 4 doubles: MI, GMI, SE_MI, SE_GMI (bits per symbol); SE is NaN for N = 1.
+ *  llr_dev:   N x m LLRs (nats), or NULL to skip the LLR output. */
+air_status air_mi_gmi(air_ctx *ctx, const air_const *c, const void *Y_dev,
+                      const uint32_t *tx_dev, int64_t N, double snr_db, air_prec prec,
+                      double *stats_dev, void *llr_dev);
+
+/* SNR sweep in one launch: for every SNR point s, y = x_t + sigma_s z.
+ *  tx_dev:      N transmitted indices into the rows of X (uint32).
+ *  Z_dev:       N x D unit-variance noise (double for AIR_FP64, else float).
+ *  snr_db_host: S SNR points in dB, S >= 1.
+ *  stats_dev:   S x 4 doubles (MI, GMI, SE_MI, SE_GMI per SNR point).
+ *  llr_dev:     S x N x m LLRs (nats), or NULL. */
+air_status air_sweep(air_ctx *ctx, const air_const *c, const uint32_t *tx_dev,
+                     const void *Z_dev, int64_t N, const double *snr_db_host, int S,
+                     air_prec prec, double *stats_dev, void *llr_dev);
+
+/* Number of (sample, SNR) items the last completed call on this context sent
+ * through the exact FP32 recomputation (0 for AIR_FP64). Synchronises. */
+int64_t air_last_recomputed(air_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBAIR_AIR_H */

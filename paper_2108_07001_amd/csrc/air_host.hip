@@ -1,0 +1,407 @@
+// air_host.hip -- the C ABI of libair (include/air.h): contexts, constellation
+// upload, argument validation, per-SNR scalars, kernel dispatch and the
+// fixed-order FP64 reduction of per-block partial sums into MI / GMI / SE.
+#include "../../include/air.h"
+#include "device_common.h"
+
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <string>
+#include <vector>
+
+namespace air {
+
+// Vector-kernel launchers, one per (type, D), defined in vec_inst_*.hip.
+using VecFn = hipError_t (*)(const DemapArgs&, int, hipStream_t);
+#define AIR_DECL(tag, D) hipError_t launch_vec_##tag##_d##D(const DemapArgs&, int, hipStream_t);
+#define AIR_DECL_ALL(tag)                                                                        \
+  AIR_DECL(tag, 1) AIR_DECL(tag, 2) AIR_DECL(tag, 3) AIR_DECL(tag, 4) AIR_DECL(tag, 5)          \
+  AIR_DECL(tag, 6) AIR_DECL(tag, 7) AIR_DECL(tag, 8) AIR_DECL(tag, 9) AIR_DECL(tag, 10)         \
+  AIR_DECL(tag, 11) AIR_DECL(tag, 12) AIR_DECL(tag, 13) AIR_DECL(tag, 14) AIR_DECL(tag, 15)     \
+  AIR_DECL(tag, 16)
+AIR_DECL_ALL(f32)
+AIR_DECL_ALL(f64)
+#undef AIR_DECL_ALL
+#undef AIR_DECL
+
+#define AIR_FN(tag, D) launch_vec_##tag##_d##D
+static const VecFn kVecF32[kMaxD + 1] = {
+    nullptr, AIR_FN(f32, 1), AIR_FN(f32, 2), AIR_FN(f32, 3), AIR_FN(f32, 4), AIR_FN(f32, 5),
+    AIR_FN(f32, 6), AIR_FN(f32, 7), AIR_FN(f32, 8), AIR_FN(f32, 9), AIR_FN(f32, 10),
+    AIR_FN(f32, 11), AIR_FN(f32, 12), AIR_FN(f32, 13), AIR_FN(f32, 14), AIR_FN(f32, 15),
+    AIR_FN(f32, 16)};
+static const VecFn kVecF64[kMaxD + 1] = {
+    nullptr, AIR_FN(f64, 1), AIR_FN(f64, 2), AIR_FN(f64, 3), AIR_FN(f64, 4), AIR_FN(f64, 5),
+    AIR_FN(f64, 6), AIR_FN(f64, 7), AIR_FN(f64, 8), AIR_FN(f64, 9), AIR_FN(f64, 10),
+    AIR_FN(f64, 11), AIR_FN(f64, 12), AIR_FN(f64, 13), AIR_FN(f64, 14), AIR_FN(f64, 15),
+    AIR_FN(f64, 16)};
+#undef AIR_FN
+
+static int vec_grid(int64_t N) {
+  int64_t g = (N + kBlock - 1) / kBlock;
+  return (int)(g < kMaxGrid ? g : kMaxGrid);
+}
+
+// Fixed-order reduction of the per-block partials of one launch (one block).
+// stats[4 s + q] for the launch's S SNR points; NaN if a tx index was invalid.
+__global__ __launch_bounds__(256) void finish_kernel(const double* __restrict__ partials, int nblocks,
+                                                     int S, int64_t N, int M, int m, double* stats,
+                                                     int* flags, unsigned long long* counters,
+                                                     int first) {
+  __shared__ double sums[kMaxSnrPerLaunch * 4];
+  for (int i = threadIdx.x; i < S * 4; i += blockDim.x) {
+    double t = 0.0;
+    for (int b = 0; b < nblocks; ++b) t += partials[(int64_t)b * S * 4 + i];
+    sums[i] = t;
+  }
+  __syncthreads();
+  const int bad = flags[0];
+  if (stats && (int)threadIdx.x < S) {
+    const int s = threadIdx.x;
+    const double n = (double)N;
+    const double su = sums[4 * s], sv = sums[4 * s + 1], suu = sums[4 * s + 2], svv = sums[4 * s + 3];
+    double mi = log2((double)M) - su / n;
+    double gmi = (double)m - sv / n;
+    double se_mi = __builtin_nan(""), se_gmi = __builtin_nan("");
+    if (N > 1) {
+      double vu = (suu - su * su / n) / (n - 1.0);
+      double vv = (svv - sv * sv / n) / (n - 1.0);
+      se_mi = sqrt((vu > 0.0 ? vu : 0.0) / n);
+      se_gmi = sqrt((vv > 0.0 ? vv : 0.0) / n);
+    }
+    if (bad) mi = gmi = se_mi = se_gmi = __builtin_nan("");
+    stats[4 * s + 0] = mi;
+    stats[4 * s + 1] = gmi;
+    stats[4 * s + 2] = se_mi;
+    stats[4 * s + 3] = se_gmi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (bad) flags[1] |= bad;
+    flags[0] = 0;
+    counters[1] = first ? counters[0] : counters[1] + counters[0];
+    counters[0] = 0;
+  }
+}
+
+}  // namespace air
+
+using namespace air;
+
+struct air_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  double* partials = nullptr;              // kMaxGrid x kMaxSnrPerLaunch x 4
+  int* flags = nullptr;                    // [0] this call's tx error, [1] sticky error
+  unsigned long long* counters = nullptr;  // [0] this launch's recomputed items, [1] last call's
+};
+
+struct air_const {
+  air_ctx* ctx = nullptr;   // creating context (a constellation is only used with it)
+  int device = 0;
+  int M = 0, D = 0, m = 0;
+  double es = 0.0;
+  double* x64 = nullptr;   // M x D, label order
+  float* x32 = nullptr;    // M x D, label order
+  uint32_t* lab = nullptr; // label of original index j
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+air_status fail(air_ctx* ctx, air_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+air_status hip_fail(air_ctx* ctx, hipError_t e, const char* what) {
+  return fail(ctx, e == hipErrorOutOfMemory ? AIR_E_NOMEM : AIR_E_DEVICE,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// A *_dev argument must be device (or managed) memory of the context's device.
+bool is_device_ptr(const air_ctx* ctx, const void* p) {
+  hipPointerAttribute_t at;
+  std::memset(&at, 0, sizeof(at));
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged) return false;
+  return at.device == ctx->device;
+}
+
+int bits_of(int M) {
+  int m = 0;
+  while ((1 << m) < M) ++m;
+  return m;
+}
+
+// Per-SNR scalars: sigma^2 = Es / (D 10^(snr_db/10)), c = 1 / (2 sigma^2 ln 2).
+void fill_snr(SnrTable& t, const air_const* c, const double* snr_db, int S) {
+  const double ln2 = 0.69314718055994530942;
+  for (int s = 0; s < S; ++s) {
+    const double snr = std::pow(10.0, snr_db[s] / 10.0);
+    const double sigma2 = c->es / ((double)c->D * snr);
+    t.sigma[s] = std::sqrt(sigma2);
+    t.c[s] = 1.0 / (2.0 * sigma2 * ln2);
+    t.sigmaf[s] = (float)t.sigma[s];
+    t.cf[s] = (float)t.c[s];
+  }
+}
+
+bool prec_ok(air_prec p) { return p == AIR_FP64 || p == AIR_FP32 || p == AIR_BF16X3 || p == AIR_FP16X3; }
+
+// Common driver of air_llr / air_mi_gmi / air_sweep.
+air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t* tx, int64_t N,
+               const double* snr_db, int S, int sweep, air_prec prec, double* stats, void* llr) {
+  if (!ctx) return AIR_E_INVAL;
+  if (!c || c->ctx != ctx) return fail(ctx, AIR_E_INVAL, "constellation is null or from another context");
+  if (!in) return fail(ctx, AIR_E_INVAL, sweep ? "Z_dev is null" : "Y_dev is null");
+  if (N < 1) return fail(ctx, AIR_E_INVAL, "N must be >= 1");
+  if (S < 1 || !snr_db) return fail(ctx, AIR_E_INVAL, "need at least one SNR point");
+  if (!prec_ok(prec)) return fail(ctx, AIR_E_INVAL, "unknown precision");
+  for (int s = 0; s < S; ++s)
+    if (!std::isfinite(snr_db[s])) return fail(ctx, AIR_E_INVAL, "SNR values must be finite");
+  if (prec == AIR_BF16X3 || prec == AIR_FP16X3)
+    return fail(ctx, AIR_E_UNSUPPORTED, "matrix-core precisions are not available in this build");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, AIR_E_DEVICE, "cannot select the context's device");
+  if (!is_device_ptr(ctx, in)) return fail(ctx, AIR_E_INVAL, "input block is not device memory of this context");
+  if (tx && !is_device_ptr(ctx, tx)) return fail(ctx, AIR_E_INVAL, "tx_dev is not device memory of this context");
+  if (stats && !is_device_ptr(ctx, stats)) return fail(ctx, AIR_E_INVAL, "stats_dev is not device memory of this context");
+  if (llr && !is_device_ptr(ctx, llr)) return fail(ctx, AIR_E_INVAL, "llr_dev is not device memory of this context");
+
+  const bool fp64 = prec == AIR_FP64;
+  const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
+  const int grid = vec_grid(N);
+  const VecFn fn = fp64 ? kVecF64[c->D] : kVecF32[c->D];
+  DemapArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.in = in;
+  a.tx = tx;
+  a.err = ctx->flags;
+  a.recomputed = ctx->counters;
+  a.partials = ctx->partials;
+  a.xl = fp64 ? (const void*)c->x64 : (const void*)c->x32;
+  a.lab = c->lab;
+  a.N = N;
+  a.llr_stride_s = N * (int64_t)c->m;
+  a.M = c->M;
+  a.m = c->m;
+  a.D = c->D;
+  a.sweep = sweep;
+  for (int s0 = 0; s0 < S; s0 += kMaxSnrPerLaunch) {
+    const int ns = (S - s0 < kMaxSnrPerLaunch) ? S - s0 : kMaxSnrPerLaunch;
+    a.S = ns;
+    fill_snr(a.snr, c, snr_db + s0, ns);
+    a.llr = llr ? (void*)((char*)llr + (size_t)s0 * N * c->m * tsz) : nullptr;
+    hipError_t e = fn(a, grid, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "demapping kernel launch");
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, ctx->stream, ctx->partials, grid, ns,
+                       N, c->M, c->m, stats ? stats + 4 * s0 : nullptr, ctx->flags, ctx->counters,
+                       s0 == 0 ? 1 : 0);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "reduction kernel launch");
+  }
+  ctx->err.clear();
+  return AIR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+air_status air_create(air_ctx** out, int device, void* hip_stream) {
+  if (!out) return AIR_E_INVAL;
+  *out = nullptr;
+  try {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return AIR_E_INVAL;
+    DeviceGuard g(device);
+    if (!g.ok) return AIR_E_DEVICE;
+    air_ctx* ctx = new air_ctx();
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipMalloc(&ctx->partials, sizeof(double) * kMaxGrid * kMaxSnrPerLaunch * 4);
+    if (e == hipSuccess) e = hipMalloc(&ctx->flags, sizeof(int) * 2);
+    if (e == hipSuccess) e = hipMalloc(&ctx->counters, sizeof(unsigned long long) * 2);
+    if (e == hipSuccess) e = hipMemset(ctx->flags, 0, sizeof(int) * 2);
+    if (e == hipSuccess) e = hipMemset(ctx->counters, 0, sizeof(unsigned long long) * 2);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      air_destroy(ctx);
+      return e == hipErrorOutOfMemory ? AIR_E_NOMEM : AIR_E_DEVICE;
+    }
+    *out = ctx;
+    return AIR_OK;
+  } catch (...) {
+    return AIR_E_NOMEM;
+  }
+}
+
+void air_destroy(air_ctx* ctx) {
+  if (!ctx) return;
+  DeviceGuard g(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipFree(ctx->partials);
+  (void)hipFree(ctx->flags);
+  (void)hipFree(ctx->counters);
+  delete ctx;
+}
+
+air_status air_set_stream(air_ctx* ctx, void* hip_stream) {
+  if (!ctx) return AIR_E_INVAL;
+  ctx->stream = (hipStream_t)hip_stream;
+  return AIR_OK;
+}
+
+const char* air_last_error(const air_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+air_status air_sync(air_ctx* ctx) {
+  if (!ctx) return AIR_E_INVAL;
+  try {
+    DeviceGuard g(ctx->device);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "stream synchronize");
+    int flags[2] = {0, 0};
+    e = hipMemcpy(flags, ctx->flags, sizeof(flags), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "read device error word");
+    if (flags[1]) {
+      const int zero = 0;
+      e = hipMemcpy(ctx->flags + 1, &zero, sizeof(int), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(ctx, e, "clear device error word");
+      return fail(ctx, AIR_E_RANGE, "a transmitted index >= M was seen; affected statistics are NaN");
+    }
+    return AIR_OK;
+  } catch (...) {
+    return fail(ctx, AIR_E_NOMEM, "host allocation failed");
+  }
+}
+
+air_status air_const_create(air_ctx* ctx, const double* X, const uint32_t* labels, int M, int D,
+                            air_const** out) {
+  if (!ctx) return AIR_E_INVAL;
+  if (!out) return fail(ctx, AIR_E_INVAL, "out is null");
+  *out = nullptr;
+  if (!X || !labels) return fail(ctx, AIR_E_INVAL, "X_host and labels_host must not be null");
+  if (M < 2 || M > 4096 || (M & (M - 1)) != 0)
+    return fail(ctx, AIR_E_INVAL, "M must be a power of two in [2, 4096]");
+  if (D < 1 || D > kMaxD) return fail(ctx, AIR_E_INVAL, "D must be in [1, 16]");
+  try {
+    std::vector<int> pos(M, -1);
+    for (int j = 0; j < M; ++j) {
+      if (labels[j] >= (uint32_t)M || pos[labels[j]] >= 0)
+        return fail(ctx, AIR_E_INVAL, "labels must be a bijection onto {0..M-1}");
+      pos[labels[j]] = j;
+    }
+    for (int64_t i = 0; i < (int64_t)M * D; ++i)
+      if (!std::isfinite(X[i])) return fail(ctx, AIR_E_INVAL, "X must be finite");
+    // label order: row l holds the point whose label is l
+    std::vector<double> x64((size_t)M * D);
+    std::vector<float> x32((size_t)M * D);
+    double es = 0.0;
+    for (int l = 0; l < M; ++l) {
+      double e = 0.0;
+      for (int d = 0; d < D; ++d) {
+        const double v = X[(size_t)pos[l] * D + d];
+        x64[(size_t)l * D + d] = v;
+        x32[(size_t)l * D + d] = (float)v;
+        e += v * v;
+      }
+      es += e;
+    }
+    es /= (double)M;
+    if (!(es > 0.0)) return fail(ctx, AIR_E_INVAL, "constellation has zero energy");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, AIR_E_DEVICE, "cannot select the context's device");
+    air_const* c = new air_const();
+    c->ctx = ctx;
+    c->device = ctx->device;
+    c->M = M;
+    c->D = D;
+    c->m = bits_of(M);
+    c->es = es;
+    hipError_t e = hipMalloc(&c->x64, sizeof(double) * M * D);
+    if (e == hipSuccess) e = hipMalloc(&c->x32, sizeof(float) * M * D);
+    if (e == hipSuccess) e = hipMalloc(&c->lab, sizeof(uint32_t) * M);
+    if (e == hipSuccess) e = hipMemcpy(c->x64, x64.data(), sizeof(double) * M * D, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->x32, x32.data(), sizeof(float) * M * D, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->lab, labels, sizeof(uint32_t) * M, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      air_const_destroy(c);
+      return hip_fail(ctx, e, "constellation upload");
+    }
+    *out = c;
+    ctx->err.clear();
+    return AIR_OK;
+  } catch (...) {
+    return fail(ctx, AIR_E_NOMEM, "host allocation failed");
+  }
+}
+
+void air_const_destroy(air_const* c) {
+  if (!c) return;
+  DeviceGuard g(c->device);
+  (void)hipFree(c->x64);
+  (void)hipFree(c->x32);
+  (void)hipFree(c->lab);
+  delete c;
+}
+
+int air_const_bits(const air_const* c) { return c ? c->m : 0; }
+
+air_status air_llr(air_ctx* ctx, const air_const* c, const void* Y_dev, int64_t N, double snr_db,
+                   air_prec prec, void* llr_dev) {
+  if (ctx && !llr_dev) return fail(ctx, AIR_E_INVAL, "llr_dev is null");
+  try {
+    return run(ctx, c, Y_dev, nullptr, N, &snr_db, 1, 0, prec, nullptr, llr_dev);
+  } catch (...) {
+    return fail(ctx, AIR_E_NOMEM, "host allocation failed");
+  }
+}
+
+air_status air_mi_gmi(air_ctx* ctx, const air_const* c, const void* Y_dev, const uint32_t* tx_dev,
+                      int64_t N, double snr_db, air_prec prec, double* stats_dev, void* llr_dev) {
+  if (ctx && (!tx_dev || !stats_dev)) return fail(ctx, AIR_E_INVAL, "tx_dev and stats_dev must not be null");
+  try {
+    return run(ctx, c, Y_dev, tx_dev, N, &snr_db, 1, 0, prec, stats_dev, llr_dev);
+  } catch (...) {
+    return fail(ctx, AIR_E_NOMEM, "host allocation failed");
+  }
+}
+
+air_status air_sweep(air_ctx* ctx, const air_const* c, const uint32_t* tx_dev, const void* Z_dev,
+                     int64_t N, const double* snr_db_host, int S, air_prec prec, double* stats_dev,
+                     void* llr_dev) {
+  if (ctx && (!tx_dev || !stats_dev)) return fail(ctx, AIR_E_INVAL, "tx_dev and stats_dev must not be null");
+  try {
+    return run(ctx, c, Z_dev, tx_dev, N, snr_db_host, S, 1, prec, stats_dev, llr_dev);
+  } catch (...) {
+    return fail(ctx, AIR_E_NOMEM, "host allocation failed");
+  }
+}
+
+int64_t air_last_recomputed(air_ctx* ctx) {
+  if (!ctx) return -1;
+  DeviceGuard g(ctx->device);
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return -1;
+  unsigned long long v[2] = {0, 0};
+  if (hipMemcpy(v, ctx->counters, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return -1;
+  return (int64_t)v[1];
+}
+
+}  // extern "C"

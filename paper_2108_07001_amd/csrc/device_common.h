@@ -1,0 +1,246 @@
+// device_common.h -- launch arguments and device helpers shared by the demapping kernels.
+//
+// Metric convention on the device: for a received point y, SNR s and
+// constellation point x_j (label order), the log2-likelihood up to a
+// sample constant is a_j = -c_s |y - x_j|^2 with c_s = 1 / (2 sigma_s^2 ln 2)
+// (sigma_s^2 = Es / (D 10^(snr_db/10)) per real dimension). The kernels
+// exponentiate arg_j = a_j + K with the fixed shift K = Emax - 1 - m of the
+// working type (126 - m for FP32, 1022 - m for FP64): a_j <= 0, so no term
+// and no sum of M terms can overflow, and no per-sample maximum pass is
+// needed. A bit side (or the total) whose sum falls below
+// starve(m) = 2^(m + Emin + guard) is "starved": terms flushed below the
+// normal range could then matter, and that entry is recomputed exactly with
+// its own maximum as shift (slow_rel). guard = 20 bits for FP32 (the flushed
+// mass is then < 2^-20 of the side), 60 for FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace air {
+
+constexpr int kMaxSnrPerLaunch = 64;
+constexpr int kMaxBits = 12;        // M <= 4096
+constexpr int kMaxD = 16;
+constexpr int kBlock = 256;         // threads per block of the vector kernels
+constexpr int kMaxGrid = 4096;      // upper bound on blocks of one demapping launch
+
+// Per-SNR scalars of one launch, passed by value in the kernel arguments.
+struct SnrTable {
+  double sigma[kMaxSnrPerLaunch];   // noise standard deviation per real dimension
+  double c[kMaxSnrPerLaunch];       // 1 / (2 sigma^2 ln 2)
+  float sigmaf[kMaxSnrPerLaunch];
+  float cf[kMaxSnrPerLaunch];
+};
+
+// Arguments of every demapping kernel.
+struct DemapArgs {
+  const void* in;                   // Y (N x D) or, in sweep mode, unit noise Z (N x D)
+  const uint32_t* tx;               // N transmitted indices into X, or nullptr
+  void* llr;                        // [S][N][m] LLRs (nats) or nullptr
+  double* partials;                 // [gridDim.x][S][4]: sum u, sum v, sum u^2, sum v^2
+  int* err;                         // set to 1 when a tx index >= M is seen
+  unsigned long long* recomputed;   // (sample, SNR) items that took the exact path
+  const void* xl;                   // M x D coordinates in label order (float or double)
+  const uint32_t* lab;              // label of original point index j
+  int64_t N;
+  int64_t llr_stride_s;             // elements between consecutive SNR planes of llr
+  int M, m, D, S;
+  int sweep;                        // 1: y = x_t + sigma_s z from `in`
+  SnrTable snr;
+};
+
+template <typename T> struct Real;
+
+template <> struct Real<float> {
+  static __device__ __forceinline__ float exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+  static __device__ __forceinline__ float log2(float x) { return __builtin_amdgcn_logf(x); }
+  static __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+  static __device__ __forceinline__ float shift(int m) { return 126.0f - (float)m; }
+  static __device__ __forceinline__ float starve(int m) { return __builtin_ldexpf(1.0f, m - 126 + 20); }
+  static __device__ __forceinline__ float ln2() { return 0.693147180559945309f; }
+  static __device__ __forceinline__ float nan() { return __builtin_nanf(""); }
+  static __device__ __forceinline__ float sigma(const SnrTable& t, int s) { return t.sigmaf[s]; }
+  static __device__ __forceinline__ float c(const SnrTable& t, int s) { return t.cf[s]; }
+};
+
+template <> struct Real<double> {
+  static __device__ __forceinline__ double exp2(double x) { return ::exp2(x); }
+  static __device__ __forceinline__ double log2(double x) { return ::log2(x); }
+  static __device__ __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+  static __device__ __forceinline__ double shift(int m) { return 1022.0 - (double)m; }
+  static __device__ __forceinline__ double starve(int m) { return __builtin_ldexp(1.0, m - 1022 + 60); }
+  static __device__ __forceinline__ double ln2() { return 0.6931471805599453094; }
+  static __device__ __forceinline__ double nan() { return __builtin_nan(""); }
+  static __device__ __forceinline__ double sigma(const SnrTable& t, int s) { return t.sigma[s]; }
+  static __device__ __forceinline__ double c(const SnrTable& t, int s) { return t.c[s]; }
+};
+
+// Received point of sample n at SNR s: read from Y, or x_t + sigma z (sweep).
+template <typename T, int D>
+__device__ __forceinline__ void load_point(const DemapArgs& a, int64_t n, int tl, T sigma, T (&y)[D]) {
+  const T* in = static_cast<const T*>(a.in) + n * D;
+  if (a.sweep) {
+    const T* xt = static_cast<const T*>(a.xl) + (int64_t)tl * D;
+#pragma unroll
+    for (int d = 0; d < D; ++d) y[d] = Real<T>::fma(sigma, in[d], xt[d]);
+  } else {
+#pragma unroll
+    for (int d = 0; d < D; ++d) y[d] = in[d];
+  }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T sqdist(const T (&y)[D], const T* __restrict__ x) {
+  T d2 = 0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    T df = y[d] - x[d];
+    d2 = Real<T>::fma(df, df, d2);
+  }
+  return d2;
+}
+
+// ---- exact recomputation (rare path) -------------------------------------
+// Used for items whose fast-path sums fall below the starvation bound. All
+// metrics are taken relative to a reference point r (the nearest point), and
+// the difference a_j - a_r = -c (|y-x_j|^2 - |y-x_r|^2) is formed as
+// -c sum_d (x_r - x_j)_d (2 y - x_r - x_j)_d, which keeps its relative
+// accuracy even when y is far from every point (|a_j| huge, difference not).
+// Out of line and reloading the received point, so that the fast path's
+// registers stay untouched.
+
+template <typename T, int D>
+__device__ __forceinline__ void reload_point(const T* __restrict__ in, int sweep,
+                                             const T* __restrict__ xl, T sigma, int64_t n, int tl,
+                                             T (&y)[D]) {
+  const T* p = in + n * D;
+  if (sweep) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) y[d] = Real<T>::fma(sigma, p[d], xl[(int64_t)tl * D + d]);
+  } else {
+#pragma unroll
+    for (int d = 0; d < D; ++d) y[d] = p[d];
+  }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T rel_metric(const T (&y)[D], const T* __restrict__ xr,
+                                        const T* __restrict__ xj, T c) {
+  T acc = 0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) acc = Real<T>::fma(xr[d] - xj[d], (y[d] - xr[d]) + (y[d] - xj[d]), acc);
+  return -c * acc;
+}
+
+// Index (label order) of the point nearest to the received point; ties to the lowest.
+template <typename T, int D>
+__device__ __noinline__ int slow_nearest(const T* __restrict__ in, int sweep, const T* __restrict__ xl,
+                                         int M, T sigma, int64_t n, int tl) {
+  T y[D];
+  reload_point<T, D>(in, sweep, xl, sigma, n, tl, y);
+  int best = 0;
+  T bd = sqdist<T, D>(y, xl);
+  for (int j = 1; j < M; ++j) {
+    T d2 = sqdist<T, D>(y, xl + (int64_t)j * D);
+    if (d2 < bd) { bd = d2; best = j; }
+  }
+  return best;
+}
+
+// log2 sum_{j in selection} 2^(a_j - a_r): bit side (k, b), all points (k = -1);
+// or a_t - a_r itself (k = -2).
+template <typename T, int D>
+__device__ __noinline__ T slow_rel(const T* __restrict__ in, int sweep, const T* __restrict__ xl,
+                                   int M, T sigma, T c, int64_t n, int tl, int r, int k, int b) {
+  T y[D];
+  reload_point<T, D>(in, sweep, xl, sigma, n, tl, y);
+  const T* xr = xl + (int64_t)r * D;
+  if (k == -2) return rel_metric<T, D>(y, xr, xl + (int64_t)tl * D, c);
+  T dmax = -__builtin_huge_val();
+  for (int j = 0; j < M; ++j) {
+    if (k >= 0 && (((j >> k) & 1) != b)) continue;
+    T dj = rel_metric<T, D>(y, xr, xl + (int64_t)j * D, c);
+    dmax = dj > dmax ? dj : dmax;
+  }
+  T sum = 0;
+  for (int j = 0; j < M; ++j) {
+    if (k >= 0 && (((j >> k) & 1) != b)) continue;
+    sum += Real<T>::exp2(rel_metric<T, D>(y, xr, xl + (int64_t)j * D, c) - dmax);
+  }
+  return dmax + Real<T>::log2(sum);
+}
+
+// Outputs of one (sample, SNR) item from its fast-path sums.
+//  total:   sum_j 2^arg_j;  side[2k+b]: the same over bit side (k, b).
+//  arg_t:   arg of the transmitted point (used when tl >= 0).
+// Writes the m LLRs (if llr_out) and returns u, v through the references.
+// Entries below the starvation bound are recomputed exactly.
+template <typename T, int D>
+__device__ __forceinline__ void finish_item(const DemapArgs& a, int64_t n, int tl, int s,
+                                            T total, const T (&side)[2 * kMaxBits], T arg_t,
+                                            T* llr_out, T& u, T& v) {
+  const int m = a.m;
+  const T thr = Real<T>::starve(m);
+  T lam[2 * kMaxBits];
+  T lam_tot;
+  bool slow = !(total >= thr);
+  lam_tot = Real<T>::log2(total);
+#pragma unroll
+  for (int i = 0; i < 2 * kMaxBits; ++i) {
+    if (i < 2 * m) {
+      slow |= !(side[i] >= thr);
+      lam[i] = Real<T>::log2(side[i]);
+    }
+  }
+  bool total_slow = false;
+  T delta_t = 0;
+  if (slow) {
+    // Starved entries are recomputed relative to the nearest point r. If the
+    // total itself is starved every entry is (each side is below the total),
+    // and all of them stay relative to a_r; otherwise the recomputed sides are
+    // put back in the fast path's units by adding K + a_r, which is then small.
+    const T* in = static_cast<const T*>(a.in);
+    const T* xl = static_cast<const T*>(a.xl);
+    const T sigma = Real<T>::sigma(a.snr, s), c = Real<T>::c(a.snr, s);
+    atomicAdd(a.recomputed, 1ull);
+    const int r = slow_nearest<T, D>(in, a.sweep, xl, a.M, sigma, n, tl);
+    total_slow = !(total >= thr);
+    T base = 0;
+    if (total_slow) {
+      lam_tot = slow_rel<T, D>(in, a.sweep, xl, a.M, sigma, c, n, tl, r, -1, 0);
+      if (tl >= 0) delta_t = slow_rel<T, D>(in, a.sweep, xl, a.M, sigma, c, n, tl, r, -2, 0);
+    } else {
+      T y[D];
+      reload_point<T, D>(in, a.sweep, xl, sigma, n, tl, y);
+      base = Real<T>::shift(m) - c * sqdist<T, D>(y, xl + (int64_t)r * D);
+    }
+#pragma unroll
+    for (int i = 0; i < 2 * kMaxBits; ++i)
+      if (i < 2 * m && !(side[i] >= thr))
+        lam[i] = base + slow_rel<T, D>(in, a.sweep, xl, a.M, sigma, c, n, tl, r, i >> 1, i & 1);
+  }
+  if (llr_out) {
+#pragma unroll
+    for (int k = 0; k < kMaxBits; ++k)
+      if (k < m) llr_out[k] = Real<T>::ln2() * (lam[2 * k] - lam[2 * k + 1]);
+  }
+  if (tl >= 0) {
+    // log2 of the very term that entered the sum (not arg_t itself): u >= 0
+    // then holds exactly, whatever the rounding of exp2 and log2.
+    u = total_slow ? lam_tot - delta_t : lam_tot - Real<T>::log2(Real<T>::exp2(arg_t));
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxBits; ++k)
+      if (k < m) acc += lam_tot - (((tl >> k) & 1) ? lam[2 * k + 1] : lam[2 * k]);
+    v = acc;
+  }
+}
+
+// Sum of a double over the 64 lanes of a wave (every lane gets the result).
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+}  // namespace air

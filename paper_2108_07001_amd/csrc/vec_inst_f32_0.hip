@@ -1,0 +1,15 @@
+// vec_inst_f32_0.hip -- instances of the vector demapping kernels
+// (float, D = 1..4); split across files so that hipcc runs in parallel.
+#include "vec_kernels.h"
+
+namespace air {
+#define AIR_VEC_INST(D) \
+  hipError_t launch_vec_f32_d##D(const DemapArgs& a, int g, hipStream_t s) { \
+    return launch_vec_td<float, D>(a, g, s); \
+  }
+AIR_VEC_INST(1)
+AIR_VEC_INST(2)
+AIR_VEC_INST(3)
+AIR_VEC_INST(4)
+#undef AIR_VEC_INST
+}  // namespace air

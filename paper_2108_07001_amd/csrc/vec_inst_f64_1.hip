@@ -1,0 +1,15 @@
+// vec_inst_f64_1.hip -- instances of the vector demapping kernels
+// (double, D = 5..8); split across files so that hipcc runs in parallel.
+#include "vec_kernels.h"
+
+namespace air {
+#define AIR_VEC_INST(D) \
+  hipError_t launch_vec_f64_d##D(const DemapArgs& a, int g, hipStream_t s) { \
+    return launch_vec_td<double, D>(a, g, s); \
+  }
+AIR_VEC_INST(5)
+AIR_VEC_INST(6)
+AIR_VEC_INST(7)
+AIR_VEC_INST(8)
+#undef AIR_VEC_INST
+}  // namespace air

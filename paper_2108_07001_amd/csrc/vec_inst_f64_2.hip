@@ -1,0 +1,15 @@
+// vec_inst_f64_2.hip -- instances of the vector demapping kernels
+// (double, D = 9..12); split across files so that hipcc runs in parallel.
+#include "vec_kernels.h"
+
+namespace air {
+#define AIR_VEC_INST(D) \
+  hipError_t launch_vec_f64_d##D(const DemapArgs& a, int g, hipStream_t s) { \
+    return launch_vec_td<double, D>(a, g, s); \
+  }
+AIR_VEC_INST(9)
+AIR_VEC_INST(10)
+AIR_VEC_INST(11)
+AIR_VEC_INST(12)
+#undef AIR_VEC_INST
+}  // namespace air
