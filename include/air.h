@@ -139,9 +139,22 @@ air_status air_sweep(air_ctx *ctx, const air_const *c, const uint32_t *tx_dev,
                      const void *Z_dev, int64_t N, const double *snr_db_host, int S,
                      air_prec prec, double *stats_dev, void *llr_dev);
 
-/* Number of (sample, SNR) items the last completed call on this context sent
- * through the exact FP32 recomputation (0 for AIR_FP64). Synchronises. */
+/* Number of (sample, SNR) items the last call on this context sent through
+ * the exact recomputation (starved bit sides: |LLR| beyond the working type's
+ * shifted range, or a received point far from every constellation point).
+ * Synchronises. Returns -1 on error. */
 int64_t air_last_recomputed(air_ctx *ctx);
+
+/* Kernel timing for measurement tools. While enabled, every call records a
+ * pair of HIP events on the context's stream around each of its demapping
+ * kernel launches (not around the small reduction kernel that follows).
+ * Enabling or disabling discards the recorded pairs. */
+air_status air_set_timing(air_ctx *ctx, int enable);
+
+/* Sum of the demapping-kernel durations recorded since timing was enabled or
+ * last read (ms), and the number of launches; synchronises, then discards the
+ * recorded pairs. */
+air_status air_kernel_time(air_ctx *ctx, double *total_ms, int64_t *launches);
 
 #ifdef __cplusplus
 }

@@ -70,6 +70,10 @@ def load() -> ctypes.CDLL:
     lib.air_sweep.restype = ci
     lib.air_last_recomputed.argtypes = [vp]
     lib.air_last_recomputed.restype = i64
+    lib.air_set_timing.argtypes = [vp, ci]
+    lib.air_set_timing.restype = ci
+    lib.air_kernel_time.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    lib.air_kernel_time.restype = ci
     _lib = lib
     return lib
 
@@ -150,6 +154,15 @@ class Context:
 
     def last_recomputed(self) -> int:
         return int(self.lib.air_last_recomputed(self.h))
+
+    def set_timing(self, enable: bool):
+        self.check(self.lib.air_set_timing(self.h, 1 if enable else 0))
+
+    def kernel_time(self):
+        """(total ms, launches) of the demapping kernels timed since the last read."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        self.check(self.lib.air_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def close(self):
         if getattr(self, "h", None):

@@ -43,45 +43,52 @@ static int vec_grid(int64_t N) {
   return (int)(g < kMaxGrid ? g : kMaxGrid);
 }
 
-// Fixed-order reduction of the per-block partials of one launch (one block).
-// stats[4 s + q] for the launch's S SNR points; NaN if a tx index was invalid.
+// Per-call device words: the tx-range error of this call and the number of
+// items sent through the exact path; cleared at the start of every call.
+struct CallWords {
+  int err;
+  int pad;
+  unsigned long long recomputed;
+};
+
+// Fixed-order reduction of the per-block partials of one launch: block s
+// reduces SNR point s; wave q of it sums quantity q over the demapping blocks
+// (lane l takes blocks l, l + 64, ...; then a fixed butterfly), so the result
+// does not depend on timing. stats[4 s + q] = MI, GMI, SE_MI, SE_GMI; NaN if
+// a tx index was invalid. Block 0 folds this call's error into the sticky word.
 __global__ __launch_bounds__(256) void finish_kernel(const double* __restrict__ partials, int nblocks,
-                                                     int S, int64_t N, int M, int m, double* stats,
-                                                     int* flags, unsigned long long* counters,
-                                                     int first) {
-  __shared__ double sums[kMaxSnrPerLaunch * 4];
-  for (int i = threadIdx.x; i < S * 4; i += blockDim.x) {
-    double t = 0.0;
-    for (int b = 0; b < nblocks; ++b) t += partials[(int64_t)b * S * 4 + i];
-    sums[i] = t;
-  }
+                                                     int64_t N, int M, int m, double* stats,
+                                                     const CallWords* call, int* sticky) {
+  __shared__ double sums[4];
+  const int s = blockIdx.x;
+  const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double* p = partials + ((int64_t)s * 4 + q) * nblocks;
+  double t = 0.0;
+  for (int b = lane; b < nblocks; b += 64) t += p[b];
+  t = wave_sum(t);
+  if (lane == 0) sums[q] = t;
   __syncthreads();
-  const int bad = flags[0];
-  if (stats && (int)threadIdx.x < S) {
-    const int s = threadIdx.x;
-    const double n = (double)N;
-    const double su = sums[4 * s], sv = sums[4 * s + 1], suu = sums[4 * s + 2], svv = sums[4 * s + 3];
-    double mi = log2((double)M) - su / n;
-    double gmi = (double)m - sv / n;
-    double se_mi = __builtin_nan(""), se_gmi = __builtin_nan("");
-    if (N > 1) {
-      double vu = (suu - su * su / n) / (n - 1.0);
-      double vv = (svv - sv * sv / n) / (n - 1.0);
-      se_mi = sqrt((vu > 0.0 ? vu : 0.0) / n);
-      se_gmi = sqrt((vv > 0.0 ? vv : 0.0) / n);
-    }
-    if (bad) mi = gmi = se_mi = se_gmi = __builtin_nan("");
-    stats[4 * s + 0] = mi;
-    stats[4 * s + 1] = gmi;
-    stats[4 * s + 2] = se_mi;
-    stats[4 * s + 3] = se_gmi;
-  }
-  __syncthreads();
+  const int bad = call->err;
   if (threadIdx.x == 0) {
-    if (bad) flags[1] |= bad;
-    flags[0] = 0;
-    counters[1] = first ? counters[0] : counters[1] + counters[0];
-    counters[0] = 0;
+    if (stats) {
+      const double n = (double)N;
+      const double su = sums[0], sv = sums[1], suu = sums[2], svv = sums[3];
+      double mi = log2((double)M) - su / n;
+      double gmi = (double)m - sv / n;
+      double se_mi = __builtin_nan(""), se_gmi = __builtin_nan("");
+      if (N > 1) {
+        const double vu = (suu - su * su / n) / (n - 1.0);
+        const double vv = (svv - sv * sv / n) / (n - 1.0);
+        se_mi = sqrt((vu > 0.0 ? vu : 0.0) / n);
+        se_gmi = sqrt((vv > 0.0 ? vv : 0.0) / n);
+      }
+      if (bad) mi = gmi = se_mi = se_gmi = __builtin_nan("");
+      stats[4 * s + 0] = mi;
+      stats[4 * s + 1] = gmi;
+      stats[4 * s + 2] = se_mi;
+      stats[4 * s + 3] = se_gmi;
+    }
+    if (s == 0 && bad) atomicOr(sticky, bad);
   }
 }
 
@@ -93,9 +100,13 @@ struct air_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
-  double* partials = nullptr;              // kMaxGrid x kMaxSnrPerLaunch x 4
-  int* flags = nullptr;                    // [0] this call's tx error, [1] sticky error
-  unsigned long long* counters = nullptr;  // [0] this launch's recomputed items, [1] last call's
+  double* partials = nullptr;    // kMaxSnrPerLaunch x 4 x kMaxGrid
+  CallWords* call = nullptr;     // this call's error word and exact-path count
+  int* sticky = nullptr;         // tx-range error seen since the last air_sync
+  // optional timing of the demapping kernels (air_set_timing)
+  bool timing = false;
+  std::vector<hipEvent_t> ev;    // start/stop pairs recorded since the last read
+  size_t ev_used = 0;
 };
 
 struct air_const {
@@ -193,8 +204,8 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
   std::memset(&a, 0, sizeof(a));
   a.in = in;
   a.tx = tx;
-  a.err = ctx->flags;
-  a.recomputed = ctx->counters;
+  a.err = &ctx->call->err;
+  a.recomputed = &ctx->call->recomputed;
   a.partials = ctx->partials;
   a.xl = fp64 ? (const void*)c->x64 : (const void*)c->x32;
   a.lab = c->lab;
@@ -204,16 +215,36 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
   a.m = c->m;
   a.D = c->D;
   a.sweep = sweep;
+  hipError_t e = hipMemsetAsync(ctx->call, 0, sizeof(CallWords), ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "clear call words");
   for (int s0 = 0; s0 < S; s0 += kMaxSnrPerLaunch) {
     const int ns = (S - s0 < kMaxSnrPerLaunch) ? S - s0 : kMaxSnrPerLaunch;
     a.S = ns;
     fill_snr(a.snr, c, snr_db + s0, ns);
     a.llr = llr ? (void*)((char*)llr + (size_t)s0 * N * c->m * tsz) : nullptr;
-    hipError_t e = fn(a, grid, ctx->stream);
+    hipEvent_t* evp = nullptr;
+    if (ctx->timing) {
+      if (ctx->ev_used + 2 > ctx->ev.size()) {
+        for (int k = 0; k < 2; ++k) {
+          hipEvent_t ev;
+          e = hipEventCreate(&ev);
+          if (e != hipSuccess) return hip_fail(ctx, e, "timing event");
+          ctx->ev.push_back(ev);
+        }
+      }
+      evp = &ctx->ev[ctx->ev_used];
+      ctx->ev_used += 2;
+      e = hipEventRecord(evp[0], ctx->stream);
+      if (e != hipSuccess) return hip_fail(ctx, e, "timing event record");
+    }
+    e = fn(a, grid, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "demapping kernel launch");
-    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, ctx->stream, ctx->partials, grid, ns,
-                       N, c->M, c->m, stats ? stats + 4 * s0 : nullptr, ctx->flags, ctx->counters,
-                       s0 == 0 ? 1 : 0);
+    if (evp) {
+      e = hipEventRecord(evp[1], ctx->stream);
+      if (e != hipSuccess) return hip_fail(ctx, e, "timing event record");
+    }
+    hipLaunchKernelGGL(finish_kernel, dim3(ns), dim3(256), 0, ctx->stream, ctx->partials, grid, N,
+                       c->M, c->m, stats ? stats + 4 * s0 : nullptr, ctx->call, ctx->sticky);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "reduction kernel launch");
   }
@@ -237,10 +268,10 @@ air_status air_create(air_ctx** out, int device, void* hip_stream) {
     ctx->device = device;
     ctx->stream = (hipStream_t)hip_stream;
     hipError_t e = hipMalloc(&ctx->partials, sizeof(double) * kMaxGrid * kMaxSnrPerLaunch * 4);
-    if (e == hipSuccess) e = hipMalloc(&ctx->flags, sizeof(int) * 2);
-    if (e == hipSuccess) e = hipMalloc(&ctx->counters, sizeof(unsigned long long) * 2);
-    if (e == hipSuccess) e = hipMemset(ctx->flags, 0, sizeof(int) * 2);
-    if (e == hipSuccess) e = hipMemset(ctx->counters, 0, sizeof(unsigned long long) * 2);
+    if (e == hipSuccess) e = hipMalloc(&ctx->call, sizeof(CallWords));
+    if (e == hipSuccess) e = hipMalloc(&ctx->sticky, sizeof(int));
+    if (e == hipSuccess) e = hipMemset(ctx->call, 0, sizeof(CallWords));
+    if (e == hipSuccess) e = hipMemset(ctx->sticky, 0, sizeof(int));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
       air_destroy(ctx);
@@ -258,8 +289,9 @@ void air_destroy(air_ctx* ctx) {
   DeviceGuard g(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   (void)hipFree(ctx->partials);
-  (void)hipFree(ctx->flags);
-  (void)hipFree(ctx->counters);
+  (void)hipFree(ctx->call);
+  (void)hipFree(ctx->sticky);
+  for (hipEvent_t ev : ctx->ev) (void)hipEventDestroy(ev);
   delete ctx;
 }
 
@@ -277,12 +309,12 @@ air_status air_sync(air_ctx* ctx) {
     DeviceGuard g(ctx->device);
     hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "stream synchronize");
-    int flags[2] = {0, 0};
-    e = hipMemcpy(flags, ctx->flags, sizeof(flags), hipMemcpyDeviceToHost);
+    int sticky = 0;
+    e = hipMemcpy(&sticky, ctx->sticky, sizeof(int), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(ctx, e, "read device error word");
-    if (flags[1]) {
+    if (sticky) {
       const int zero = 0;
-      e = hipMemcpy(ctx->flags + 1, &zero, sizeof(int), hipMemcpyHostToDevice);
+      e = hipMemcpy(ctx->sticky, &zero, sizeof(int), hipMemcpyHostToDevice);
       if (e != hipSuccess) return hip_fail(ctx, e, "clear device error word");
       return fail(ctx, AIR_E_RANGE, "a transmitted index >= M was seen; affected statistics are NaN");
     }
@@ -399,9 +431,35 @@ int64_t air_last_recomputed(air_ctx* ctx) {
   if (!ctx) return -1;
   DeviceGuard g(ctx->device);
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return -1;
-  unsigned long long v[2] = {0, 0};
-  if (hipMemcpy(v, ctx->counters, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return -1;
-  return (int64_t)v[1];
+  CallWords w;
+  if (hipMemcpy(&w, ctx->call, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess) return -1;
+  return (int64_t)w.recomputed;
+}
+
+air_status air_set_timing(air_ctx* ctx, int enable) {
+  if (!ctx) return AIR_E_INVAL;
+  ctx->timing = enable != 0;
+  ctx->ev_used = 0;
+  return AIR_OK;
+}
+
+air_status air_kernel_time(air_ctx* ctx, double* total_ms, int64_t* launches) {
+  if (!ctx) return AIR_E_INVAL;
+  if (!total_ms || !launches) return fail(ctx, AIR_E_INVAL, "null output pointer");
+  DeviceGuard g(ctx->device);
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "stream synchronize");
+  double t = 0.0;
+  for (size_t i = 0; i + 1 < ctx->ev_used; i += 2) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]);
+    if (e != hipSuccess) return hip_fail(ctx, e, "event elapsed time");
+    t += ms;
+  }
+  *total_ms = t;
+  *launches = (int64_t)(ctx->ev_used / 2);
+  ctx->ev_used = 0;
+  return AIR_OK;
 }
 
 }  // extern "C"

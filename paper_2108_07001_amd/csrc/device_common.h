@@ -22,7 +22,7 @@ constexpr int kMaxSnrPerLaunch = 64;
 constexpr int kMaxBits = 12;        // M <= 4096
 constexpr int kMaxD = 16;
 constexpr int kBlock = 256;         // threads per block of the vector kernels
-constexpr int kMaxGrid = 4096;      // upper bound on blocks of one demapping launch
+constexpr int kMaxGrid = 1024;      // upper bound on blocks of one demapping launch
 
 // Per-SNR scalars of one launch, passed by value in the kernel arguments.
 struct SnrTable {
@@ -37,7 +37,7 @@ struct DemapArgs {
   const void* in;                   // Y (N x D) or, in sweep mode, unit noise Z (N x D)
   const uint32_t* tx;               // N transmitted indices into X, or nullptr
   void* llr;                        // [S][N][m] LLRs (nats) or nullptr
-  double* partials;                 // [gridDim.x][S][4]: sum u, sum v, sum u^2, sum v^2
+  double* partials;                 // [S][4][gridDim.x]: sum u, sum v, sum u^2, sum v^2
   int* err;                         // set to 1 when a tx index >= M is seen
   unsigned long long* recomputed;   // (sample, SNR) items that took the exact path
   const void* xl;                   // M x D coordinates in label order (float or double)

@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void demap_vec(const DemapArgs a, const T* 
   for (int i = threadIdx.x; i < S * 4; i += blockDim.x) {
     double t = 0.0;
     for (int w = 0; w < waves; ++w) t += acc_lds[w * S * 4 + i];
-    a.partials[(int64_t)blockIdx.x * S * 4 + i] = t;
+    a.partials[(int64_t)i * gridDim.x + blockIdx.x] = t;
   }
 }
 
