@@ -31,6 +31,89 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def serving(ctx, n_jobs: int) -> dict:
+    """Replay the Poisson serving mix through the serving loop: each job is
+    submitted at its arrival time and its latency runs from that time to the
+    moment its MI/GMI are on the host (LLRs stay in device memory). Inputs are
+    slices of pinned host pools (unit noise and tx: their host-to-device copy
+    is inside the latency) or, in a second pass, of device-resident pools."""
+    import torch
+    from paper_2108_07001_amd import inputs
+    spec = inputs.SERVING
+    jobs = inputs.serving_jobs(n_jobs)
+    Ms = sorted(spec["M_choices"])
+    pools = {M: [ctx.const(X, lab) for X, lab in inputs.serving_pool(M)] for M in Ms}
+    nmax = max(j.N for j in jobs)
+    r = np.random.default_rng(spec["seed"] + 1)
+    Ds = sorted(set(spec["D_for_M"][M] for M in Ms))
+    z_host = {D: torch.from_numpy(r.standard_normal((nmax, D)).astype(np.float32)).pin_memory() for D in Ds}
+    tx_host = {M: torch.from_numpy(r.integers(0, M, nmax).astype(np.int32)).pin_memory() for M in Ms}
+    dev = ctx.torch_device
+    z_dev = {D: t.to(dev) for D, t in z_host.items()}
+    tx_dev = {M: t.to(dev) for M, t in tx_host.items()}
+    # device LLR slots, one per job in flight (handed back when its result is polled)
+    mmax = max(int(np.log2(M)) for M in Ms)
+    nslots = 128
+    llr_pool = torch.empty((nslots, nmax * mmax), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+
+    def replay(on_device: bool) -> dict:
+        sv = ctx.server(16 << 30, max_inflight=nslots)
+        free = list(range(nslots))
+        slot_of, done = {}, []
+
+        def reap():
+            for res in sv.poll(1024):
+                free.append(slot_of.pop(res["id"]))
+                done.append(res)
+
+        t0 = time.monotonic_ns() + 20_000_000
+        for jb in jobs:
+            c = pools[jb.M][jb.const_id]
+            while not free:
+                reap()
+            k = free.pop()
+            t_arr = t0 + int(jb.arrival_s * 1e9)
+            while time.monotonic_ns() < t_arr:
+                reap()
+            zsrc = z_dev if on_device else z_host
+            txsrc = tx_dev if on_device else tx_host
+            L = llr_pool[k, :jb.N * c.m].view(jb.N, c.m)
+            jid = sv.submit(c=c, inp=zsrc[jb.D][:jb.N], tx=txsrc[jb.M][:jb.N], snr_db=jb.snr_db,
+                            noise=True, prec="fp16x3", llr=L, t_arrival_ns=t_arr)
+            slot_of[jid] = k
+        sv.drain()
+        reap()
+        info = sv.info()
+        sv.close()
+        lat = np.array([(x["t_done_ns"] - x["t_arrival_ns"]) * 1e-6 for x in done])
+        wait = np.array([(x["t_launch_ns"] - x["t_arrival_ns"]) * 1e-6 for x in done])
+        bad = sum(1 for x in done if x["status"] != 0)
+        span = (max(x["t_done_ns"] for x in done) - t0) * 1e-9
+        pts = sum(j.N * j.M for j in jobs)
+        return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "max_ms": float(lat.max()), "mean_ms": float(lat.mean()),
+                "p99_wait_to_launch_ms": float(np.percentile(wait, 99)),
+                "jobs": len(done), "failed": bad, "batches": int(info["batches"]),
+                "max_batch": int(info["max_batch"]), "peak_arena_bytes": int(info["peak_in_use"]),
+                "offered_sample_points_per_s": pts / jobs[-1].arrival_s,
+                "achieved_sample_points_per_s": pts / span}
+
+    log(f"serving: {n_jobs} jobs, host inputs")
+    host = replay(False)
+    log(f"serving host inputs: p50 {host['p50_ms']:.3f} ms, p99 {host['p99_ms']:.3f} ms")
+    devr = replay(True)
+    log(f"serving device inputs: p50 {devr['p50_ms']:.3f} ms, p99 {devr['p99_ms']:.3f} ms")
+    for p in pools.values():
+        for c in p:
+            c.close()
+    return {"workload": f"Poisson {spec['rate_hz']:g} jobs/s, M in {list(Ms)} (D {spec['D_for_M']}), "
+                        f"N = 10^U({spec['N_log10'][0]},{spec['N_log10'][1]}), SNR U{tuple(spec['snr_db'])} dB, "
+                        f"fp16x3, LLRs to device memory",
+            "latency_from": "arrival time -> MI/GMI on the host",
+            "host_inputs": host, "device_inputs": devr}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -41,7 +124,24 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip timing the plain FP32 kernel beside the matrix-core form")
+    ap.add_argument("--serving-jobs", type=int, default=4000,
+                    help="jobs of the Poisson serving mix to replay (0: skip; full mix: 20000)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device-to-device copy of 1 GiB (3 times), the "
+                         "reference for scaling hardware byte counters")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read_per_launch": a.numel() * 4,
+                          "copy_probe_bytes_written_per_launch": b.numel() * 4, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
@@ -68,6 +168,7 @@ def main():
         for _ in range(warmup):
             ctx.sweep(c, tx, zt, w.snr_db, prec=prec, stats_out=stats, llr_out=L)
         ctx.sync()
+        log(f"{prec}: warmup done")
         recomputed = ctx.last_recomputed()
         ctx.set_timing(True)
         torch.cuda.synchronize()
@@ -95,7 +196,7 @@ def main():
             if e.status != air.AIR_E_UNSUPPORTED:
                 raise
             log(f"{p}: not available ({e})")
-    if "fp32" not in results:
+    if "fp32" not in results and not args.no_fp32:
         results["fp32"] = run_prec("fp32", max(3, args.steps // 4), 1)
 
     r = results[chosen]
@@ -127,11 +228,14 @@ def main():
                      "per_unit": f"(M + 2m + 1) = {M + 2 * m + 1} exp2/log2 per sample per SNR"},
         "exact_path_items": int(r["recomputed"]),
     }
-    if chosen != "fp32":
+    if chosen != "fp32" and "fp32" in results:
         f = results["fp32"]
         line["fp32_plain"] = {"value": pts / (f["ms"] * 1e-3), "ms_per_step": f["ms"],
                               "kernel_ms": f["kernel_ms"]}
         line["speedup_vs_fp32"] = f["ms"] / r["ms"]
+
+    if args.serving_jobs > 0:
+        line["serving"] = serving(ctx, args.serving_jobs)
 
     if not args.no_cpu:
         import oracle

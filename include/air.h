@@ -156,6 +156,97 @@ air_status air_set_timing(air_ctx *ctx, int enable);
  * recorded pairs. */
 air_status air_kernel_time(air_ctx *ctx, double *total_ms, int64_t *launches);
 
+/* ---------------------------------------------------------------------------
+ * Serving loop. Demapping jobs of uneven size (constellation, N, SNR) arrive
+ * at any time, the way a software receiver hands over one buffer after
+ * another (the paper streams buffers of samples to the GPU and gives each
+ * buffer its own stream, trading buffer size against latency; Section II).
+ * A server owns one device arena of a fixed byte budget, allocated at
+ * creation, and a worker thread that
+ *  - admits jobs in arrival order while their footprint fits in the arena
+ *    and fewer than max_inflight jobs are admitted or running; the footprint
+ *    is the job's staged inputs (host Y / Z and tx), staged LLRs (host llr),
+ *    and its per-item FP64 partial sums and tile lists;
+ *  - batches whatever is admitted when one of its launch slots (one stream
+ *    each) is free, and runs the batch: input copies, the batched
+ *    matrix-core kernels (one launch per kernel class of jobs), a
+ *    fixed-order reduction per job, result copies;
+ *  - stamps completion when the batch's event has completed and queues the
+ *    results for air_server_poll.
+ * Each job's reduction order is fixed by the job alone, so its statistics
+ * and LLRs are bitwise the same whether it runs alone or in any mix.
+ * Jobs use the matrix-core forms (AIR_FP16X3, AIR_BF16X3) with M >= 16.
+ * A server must be destroyed before its context; a job's constellation and
+ * buffers must stay valid until its result has been polled.
+ * ------------------------------------------------------------------------- */
+typedef struct air_server air_server;
+
+typedef struct {
+  const air_const *c;    /* constellation (created on the server's context) */
+  const float *in;       /* N x D float: received points y, or unit noise z if noise_in;
+                            device memory of the context, or host memory (pinned
+                            memory copies asynchronously; pageable memory works) */
+  const uint32_t *tx;    /* N transmitted indices (device or host), or NULL: LLRs
+                            only, the statistics are NaN */
+  int64_t N;             /* samples, >= 1 */
+  double snr_db;
+  int32_t noise_in;      /* 1: in holds z and y = x_tx + sigma z is formed on the device */
+  int32_t prec;          /* air_prec: AIR_FP16X3 or AIR_BF16X3 */
+  float *llr;            /* N x m LLRs (nats): device or host memory, or NULL */
+  uint64_t t_arrival_ns; /* arrival time on the steady clock (CLOCK_MONOTONIC);
+                            0 = stamped at submission */
+  uint64_t tag;          /* caller's value, returned with the result */
+} air_job;
+
+typedef struct {
+  uint64_t id, tag;
+  int32_t status;        /* air_status: AIR_OK; AIR_E_RANGE (a tx index >= M was seen:
+                            statistics NaN, LLRs of those samples NaN); AIR_E_DEVICE */
+  int32_t pad;
+  double mi, gmi, se_mi, se_gmi;   /* bits per symbol, as air_mi_gmi */
+  uint64_t recomputed;   /* samples finished by the second tier or the exact path */
+  uint64_t t_arrival_ns, t_admit_ns, t_launch_ns, t_done_ns;   /* steady clock */
+  uint64_t footprint;    /* arena bytes the job held from admission to completion */
+} air_result;
+
+typedef struct {
+  uint64_t submitted, completed, batches;
+  uint64_t in_use, peak_in_use, budget;   /* arena bytes */
+  int32_t max_batch;     /* most jobs in one launch so far */
+  int32_t queued;        /* jobs waiting for admission */
+} air_server_info;
+
+/* Create a server on ctx's device with an arena of hbm_budget_bytes (>= 4096)
+ * and at most max_inflight (>= 1) jobs admitted or running at a time. */
+air_status air_server_create(air_ctx *ctx, size_t hbm_budget_bytes, int max_inflight,
+                             air_server **out);
+
+/* Queue one job; *id_out receives its id (> 0). Returns at once: the job
+ * waits for admission inside the server. AIR_E_NOMEM if its footprint alone
+ * exceeds the budget, AIR_E_UNSUPPORTED for a precision or M the serving
+ * kernels do not cover, AIR_E_INVAL for invalid fields, AIR_E_DEVICE after a
+ * device failure of the server, AIR_E_BUSY while it shuts down. The message
+ * is in air_server_last_error (one submitting thread at a time). */
+air_status air_server_submit(air_server *s, const air_job *job, uint64_t *id_out);
+
+/* Move up to max finished results into out (completion order); returns how
+ * many, or a negative air_status for invalid arguments. Never blocks. */
+int air_server_poll(air_server *s, air_result *out, int max);
+
+/* Wait until every submitted job has finished (timeout_ms < 0: no limit).
+ * AIR_E_BUSY on timeout; AIR_E_DEVICE if the server failed. */
+air_status air_server_drain(air_server *s, int timeout_ms);
+
+/* Counters of the server (see air_server_info). */
+air_status air_server_query(air_server *s, air_server_info *info);
+
+/* Message of the last failed submission ("" if none). Owned by the server. */
+const char *air_server_last_error(const air_server *s);
+
+/* Finish every submitted job, stop the worker and release the arena and
+ * streams. Results not yet polled are discarded. NULL is ignored. */
+void air_server_destroy(air_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,6 +29,32 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
 _lib = None
 
 
+class AirJob(ctypes.Structure):
+    """air_job of include/air.h."""
+    _fields_ = [("c", ctypes.c_void_p), ("in_", ctypes.c_void_p), ("tx", ctypes.c_void_p),
+                ("N", ctypes.c_int64), ("snr_db", ctypes.c_double), ("noise_in", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("llr", ctypes.c_void_p),
+                ("t_arrival_ns", ctypes.c_uint64), ("tag", ctypes.c_uint64)]
+
+
+class AirResult(ctypes.Structure):
+    """air_result of include/air.h."""
+    _fields_ = [("id", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("mi", ctypes.c_double), ("gmi", ctypes.c_double),
+                ("se_mi", ctypes.c_double), ("se_gmi", ctypes.c_double),
+                ("recomputed", ctypes.c_uint64), ("t_arrival_ns", ctypes.c_uint64),
+                ("t_admit_ns", ctypes.c_uint64), ("t_launch_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64), ("footprint", ctypes.c_uint64)]
+
+
+class AirServerInfo(ctypes.Structure):
+    """air_server_info of include/air.h."""
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("in_use", ctypes.c_uint64),
+                ("peak_in_use", ctypes.c_uint64), ("budget", ctypes.c_uint64),
+                ("max_batch", ctypes.c_int32), ("queued", ctypes.c_int32)]
+
+
 class AirError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -74,6 +100,20 @@ def load() -> ctypes.CDLL:
     lib.air_set_timing.restype = ci
     lib.air_kernel_time.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     lib.air_kernel_time.restype = ci
+    lib.air_server_create.argtypes = [vp, ctypes.c_size_t, ci, pvp]
+    lib.air_server_create.restype = ci
+    lib.air_server_submit.argtypes = [vp, ctypes.POINTER(AirJob), ctypes.POINTER(ctypes.c_uint64)]
+    lib.air_server_submit.restype = ci
+    lib.air_server_poll.argtypes = [vp, ctypes.POINTER(AirResult), ci]
+    lib.air_server_poll.restype = ci
+    lib.air_server_drain.argtypes = [vp, ci]
+    lib.air_server_drain.restype = ci
+    lib.air_server_query.argtypes = [vp, ctypes.POINTER(AirServerInfo)]
+    lib.air_server_query.restype = ci
+    lib.air_server_last_error.argtypes = [vp]
+    lib.air_server_last_error.restype = ctypes.c_char_p
+    lib.air_server_destroy.argtypes = [vp]
+    lib.air_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -140,6 +180,7 @@ class Context:
         self.h = h
         self.torch_device = torch.device("cuda", self.device)
         self._consts = weakref.WeakSet()
+        self._servers = weakref.WeakSet()
 
     # -- plumbing -----------------------------------------------------------
     def check(self, st: int):
@@ -166,6 +207,8 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
+            for sv in list(self._servers):
+                sv.close()
             for c in list(self._consts):
                 c.close()
             self.lib.air_destroy(self.h)
@@ -181,6 +224,11 @@ class Context:
 
     def const(self, X, labels) -> Const:
         return Const(self, X, labels)
+
+    def server(self, budget_bytes: int, max_inflight: int = 256) -> "Server":
+        sv = Server(self, budget_bytes, max_inflight)
+        self._servers.add(sv)
+        return sv
 
     def _dtype(self, prec: str):
         return torch.float64 if prec == "fp64" else torch.float32
@@ -239,6 +287,111 @@ class Context:
         self.check(self.lib.air_sweep(self.h, c.h, _ptr(tx), _ptr(Z), N, snr.ctypes.data, S,
                                       PREC[prec], _ptr(stats), _ptr(L)))
         return stats, L
+
+
+def _buffer(x, dtype, shape, name: str, device: torch.device):
+    """Address of a job buffer: a contiguous tensor (on the server's device or on
+    the host) or a C-contiguous numpy array, of the given dtype and shape."""
+    if isinstance(x, torch.Tensor):
+        ok_dev = x.device == device or x.device.type == "cpu"
+        if not ok_dev or x.dtype != dtype or tuple(x.shape) != shape or not x.is_contiguous():
+            raise AirError(AIR_E_INVAL, f"{name} must be a contiguous {dtype} tensor of shape {shape} "
+                                        f"on {device} or the host")
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        npd = {torch.float32: np.float32, torch.int32: np.int32}[dtype]
+        if x.dtype not in (npd, np.uint32 if npd is np.int32 else npd) or x.shape != shape \
+                or not x.flags.c_contiguous:
+            raise AirError(AIR_E_INVAL, f"{name} must be a C-contiguous {npd.__name__} array of shape {shape}")
+        return x.ctypes.data
+    raise AirError(AIR_E_INVAL, f"{name} must be a tensor or numpy array")
+
+
+class Server:
+    """The serving loop (air_server_*): jobs are queued with submit() and their
+    results collected with poll() / results(). Buffers handed to a job are kept
+    referenced here until its result has been polled."""
+
+    def __init__(self, ctx: Context, budget_bytes: int, max_inflight: int = 256):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        h = ctypes.c_void_p()
+        ctx.check(self.lib.air_server_create(ctx.h, int(budget_bytes), int(max_inflight), ctypes.byref(h)))
+        self.h = h
+        self._held = {}
+
+    def check(self, st: int):
+        if st != AIR_OK:
+            raise AirError(st, self.lib.air_server_last_error(self.h).decode())
+
+    def submit(self, c: Const, inp, snr_db: float, tx=None, prec: str = "fp16x3",
+               noise: bool = False, llr=None, t_arrival_ns: int = 0, tag: int = 0) -> int:
+        """Queue a job. inp: N x D float32 received points (or unit noise with
+        noise=True); tx: N int32 indices or None; llr: N x m float32 output or None.
+        Each may be a tensor on the device or on the host, or a numpy array."""
+        N = int(inp.shape[0])
+        j = AirJob()
+        j.c = c.h.value
+        j.in_ = _buffer(inp, torch.float32, (N, c.D), "inp", self.ctx.torch_device)
+        j.tx = None if tx is None else _buffer(tx, torch.int32, (N,), "tx", self.ctx.torch_device)
+        j.N = N
+        j.snr_db = float(snr_db)
+        j.noise_in = 1 if noise else 0
+        j.prec = PREC[prec]
+        j.llr = None if llr is None else _buffer(llr, torch.float32, (N, c.m), "llr", self.ctx.torch_device)
+        j.t_arrival_ns = int(t_arrival_ns)
+        j.tag = int(tag)
+        jid = ctypes.c_uint64()
+        self.check(self.lib.air_server_submit(self.h, ctypes.byref(j), ctypes.byref(jid)))
+        self._held[jid.value] = (c, inp, tx, llr)
+        return jid.value
+
+    def poll(self, max_results: int = 256) -> list:
+        """Finished results (dicts), at most max_results; never blocks."""
+        buf = (AirResult * max_results)()
+        n = self.lib.air_server_poll(self.h, buf, max_results)
+        if n < 0:
+            raise AirError(n, "air_server_poll failed")
+        out = []
+        for r in buf[:n]:
+            d = {k: getattr(r, k) for k, _ in AirResult._fields_ if k != "pad"}
+            self._held.pop(r.id, None)
+            out.append(d)
+        return out
+
+    def drain(self, timeout_ms: int = -1):
+        st = self.lib.air_server_drain(self.h, int(timeout_ms))
+        if st != AIR_OK:
+            raise AirError(st, "air_server_drain")
+
+    def results(self, timeout_ms: int = -1) -> list:
+        """Drain, then every result not yet polled."""
+        self.drain(timeout_ms)
+        out = []
+        while True:
+            part = self.poll(1024)
+            out += part
+            if len(part) < 1024:
+                return out
+
+    def info(self) -> dict:
+        inf = AirServerInfo()
+        self.check(self.lib.air_server_query(self.h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in AirServerInfo._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.air_server_destroy(self.h)
+            self.h = None
+            self._held.clear()
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # Flat aliases with the C names.

@@ -20,7 +20,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 arithmetic is disabled: hipcc would otherwise form v_pk_* FP32
 # instructions on its own.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # matrix-core results straight into VGPRs (no accumulator-register copies)
+         "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def _compile(src: str, verbose: bool) -> str:

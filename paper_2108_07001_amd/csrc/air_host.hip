@@ -3,6 +3,8 @@
 // fixed-order FP64 reduction of per-block partial sums into MI / GMI / SE.
 #include "../../include/air.h"
 #include "device_common.h"
+#include "host_state.h"
+#include "mfma_kernels.h"
 
 #include <cmath>
 #include <cstring>
@@ -38,33 +40,61 @@ static const VecFn kVecF64[kMaxD + 1] = {
     AIR_FN(f64, 16)};
 #undef AIR_FN
 
+// Matrix-core launchers, one per (operand type, D), defined in mfma_inst_*.hip.
+using MfmaFn = hipError_t (*)(const DemapArgs&, const void*, int, hipStream_t);
+#define AIR_DECL(tag, D) hipError_t launch_mfma_##tag##_d##D(const DemapArgs&, const void*, int, hipStream_t);
+#define AIR_DECL_ALL(tag)                                                                        \
+  AIR_DECL(tag, 1) AIR_DECL(tag, 2) AIR_DECL(tag, 3) AIR_DECL(tag, 4) AIR_DECL(tag, 5)          \
+  AIR_DECL(tag, 6) AIR_DECL(tag, 7) AIR_DECL(tag, 8) AIR_DECL(tag, 9) AIR_DECL(tag, 10)         \
+  AIR_DECL(tag, 11) AIR_DECL(tag, 12) AIR_DECL(tag, 13) AIR_DECL(tag, 14) AIR_DECL(tag, 15)     \
+  AIR_DECL(tag, 16)
+AIR_DECL_ALL(f16)
+AIR_DECL_ALL(bf16)
+#undef AIR_DECL_ALL
+#undef AIR_DECL
+#define AIR_FN(tag, D) launch_mfma_##tag##_d##D
+static const MfmaFn kMfmaF16[kMaxD + 1] = {
+    nullptr, AIR_FN(f16, 1), AIR_FN(f16, 2), AIR_FN(f16, 3), AIR_FN(f16, 4), AIR_FN(f16, 5),
+    AIR_FN(f16, 6), AIR_FN(f16, 7), AIR_FN(f16, 8), AIR_FN(f16, 9), AIR_FN(f16, 10),
+    AIR_FN(f16, 11), AIR_FN(f16, 12), AIR_FN(f16, 13), AIR_FN(f16, 14), AIR_FN(f16, 15),
+    AIR_FN(f16, 16)};
+static const MfmaFn kMfmaBF16[kMaxD + 1] = {
+    nullptr, AIR_FN(bf16, 1), AIR_FN(bf16, 2), AIR_FN(bf16, 3), AIR_FN(bf16, 4), AIR_FN(bf16, 5),
+    AIR_FN(bf16, 6), AIR_FN(bf16, 7), AIR_FN(bf16, 8), AIR_FN(bf16, 9), AIR_FN(bf16, 10),
+    AIR_FN(bf16, 11), AIR_FN(bf16, 12), AIR_FN(bf16, 13), AIR_FN(bf16, 14), AIR_FN(bf16, 15),
+    AIR_FN(bf16, 16)};
+#undef AIR_FN
+
+// Grid of a matrix-core launch: 4 waves per block, one 32-sample tile per wave and round.
+static int mfma_grid(int64_t N) {
+  int64_t tiles = (N + 31) / 32;
+  int64_t g = (tiles + 3) / 4;
+  return (int)(g < kMaxGrid ? g : kMaxGrid);
+}
+
 static int vec_grid(int64_t N) {
   int64_t g = (N + kBlock - 1) / kBlock;
   return (int)(g < kMaxGrid ? g : kMaxGrid);
 }
-
-// Per-call device words: the tx-range error of this call and the number of
-// items sent through the exact path; cleared at the start of every call.
-struct CallWords {
-  int err;
-  int pad;
-  unsigned long long recomputed;
-};
 
 // Fixed-order reduction of the per-block partials of one launch: block s
 // reduces SNR point s; wave q of it sums quantity q over the demapping blocks
 // (lane l takes blocks l, l + 64, ...; then a fixed butterfly), so the result
 // does not depend on timing. stats[4 s + q] = MI, GMI, SE_MI, SE_GMI; NaN if
 // a tx index was invalid. Block 0 folds this call's error into the sticky word.
-__global__ __launch_bounds__(256) void finish_kernel(const double* __restrict__ partials, int nblocks,
-                                                     int64_t N, int M, int m, double* stats,
-                                                     const CallWords* call, int* sticky) {
+__global__ __launch_bounds__(256) void finish_kernel(const double* __restrict__ partials,
+                                                     const double* __restrict__ t2_partials,
+                                                     int nblocks, int64_t N, int M, int m,
+                                                     double* stats, const CallWords* call,
+                                                     int* sticky) {
   __shared__ double sums[4];
   const int s = blockIdx.x;
   const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const double* p = partials + ((int64_t)s * 4 + q) * nblocks;
+  const int64_t off = ((int64_t)s * 4 + q) * nblocks;
   double t = 0.0;
-  for (int b = lane; b < nblocks; b += 64) t += p[b];
+  for (int b = lane; b < nblocks; b += 64) t += partials[off + b];
+  if (t2_partials)
+    for (int b = lane; b < nblocks; b += 64) t += t2_partials[off + b];
   t = wave_sum(t);
   if (lane == 0) sums[q] = t;
   __syncthreads();
@@ -96,64 +126,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const double* __restrict__ 
 
 using namespace air;
 
-struct air_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  std::string err;
-  double* partials = nullptr;    // kMaxSnrPerLaunch x 4 x kMaxGrid
-  CallWords* call = nullptr;     // this call's error word and exact-path count
-  int* sticky = nullptr;         // tx-range error seen since the last air_sync
-  // optional timing of the demapping kernels (air_set_timing)
-  bool timing = false;
-  std::vector<hipEvent_t> ev;    // start/stop pairs recorded since the last read
-  size_t ev_used = 0;
-};
-
-struct air_const {
-  air_ctx* ctx = nullptr;   // creating context (a constellation is only used with it)
-  int device = 0;
-  int M = 0, D = 0, m = 0;
-  double es = 0.0;
-  double* x64 = nullptr;   // M x D, label order
-  float* x32 = nullptr;    // M x D, label order
-  uint32_t* lab = nullptr; // label of original index j
-};
-
 namespace {
-
-struct DeviceGuard {
-  int prev = -1;
-  bool ok = false;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    ok = hipSetDevice(dev) == hipSuccess;
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
-
-air_status fail(air_ctx* ctx, air_status st, const std::string& msg) {
-  if (ctx) ctx->err = msg;
-  return st;
-}
-
-air_status hip_fail(air_ctx* ctx, hipError_t e, const char* what) {
-  return fail(ctx, e == hipErrorOutOfMemory ? AIR_E_NOMEM : AIR_E_DEVICE,
-              std::string(what) + ": " + hipGetErrorString(e));
-}
-
-// A *_dev argument must be device (or managed) memory of the context's device.
-bool is_device_ptr(const air_ctx* ctx, const void* p) {
-  hipPointerAttribute_t at;
-  std::memset(&at, 0, sizeof(at));
-  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged) return false;
-  return at.device == ctx->device;
-}
 
 int bits_of(int M) {
   int m = 0;
@@ -161,17 +134,87 @@ int bits_of(int M) {
   return m;
 }
 
-// Per-SNR scalars: sigma^2 = Es / (D 10^(snr_db/10)), c = 1 / (2 sigma^2 ln 2).
+// Round-to-nearest-even conversions of a double to half / bfloat16 bits.
+uint16_t to_f16_bits(double v) {
+  _Float16 h = (_Float16)v;
+  uint16_t b;
+  std::memcpy(&b, &h, 2);
+  return b;
+}
+double from_f16_bits(uint16_t b) {
+  _Float16 h;
+  std::memcpy(&h, &b, 2);
+  return (double)h;
+}
+uint16_t to_bf16_bits(double v) {
+  float f = (float)v;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+double from_bf16_bits(uint16_t b) {
+  uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return (double)f;
+}
+
+// Point side of the matrix-core K slots for one point x (length D), in the
+// order [x_hi | x_lo | x_hi | q_hi, q_lo, q_hi | 0...], q = |x|^2, as
+// operand bits; hi = round(v), lo = round(v - hi).
+void point_record(const double* x, int D, bool bf, uint16_t* out) {
+  const int kp = 16 * mfma_nk(D);
+  auto cv = [bf](double v) { return bf ? to_bf16_bits(v) : to_f16_bits(v); };
+  auto back = [bf](uint16_t b) { return bf ? from_bf16_bits(b) : from_f16_bits(b); };
+  for (int k = 0; k < kp; ++k) out[k] = 0;
+  double q = 0.0;
+  for (int d = 0; d < D; ++d) {
+    const uint16_t hi = cv(x[d]);
+    const uint16_t lo = cv(x[d] - back(hi));
+    out[d] = hi;
+    out[D + d] = lo;
+    out[2 * D + d] = hi;
+    q += x[d] * x[d];
+  }
+  const uint16_t qh = cv(q);
+  const uint16_t ql = cv(q - back(qh));
+  out[3 * D] = qh;
+  out[3 * D + 1] = ql;
+  out[3 * D + 2] = qh;
+}
+
+// Per-SNR scalars of one launch.
 void fill_snr(SnrTable& t, const air_const* c, const double* snr_db, int S) {
-  const double ln2 = 0.69314718055994530942;
   for (int s = 0; s < S; ++s) {
-    const double snr = std::pow(10.0, snr_db[s] / 10.0);
-    const double sigma2 = c->es / ((double)c->D * snr);
-    t.sigma[s] = std::sqrt(sigma2);
-    t.c[s] = 1.0 / (2.0 * sigma2 * ln2);
+    snr_scalars(c, snr_db[s], t.sigma[s], t.c[s]);
     t.sigmaf[s] = (float)t.sigma[s];
     t.cf[s] = (float)t.c[s];
   }
+}
+
+// Second-tier workspace: `slots` list entries and `counts` per-wave counters;
+// grows on demand and is kept, so repeated calls of one size allocate nothing.
+air_status ensure_t2(air_ctx* ctx, int64_t slots, int64_t counts) {
+  if (slots <= ctx->t2_slots && counts <= ctx->t2_counts) return AIR_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipFree(ctx->t2_list);
+  (void)hipFree(ctx->t2_count);
+  ctx->t2_list = nullptr;
+  ctx->t2_count = nullptr;
+  ctx->t2_slots = ctx->t2_counts = 0;
+  hipError_t e = hipMalloc(&ctx->t2_list, sizeof(unsigned long long) * slots);
+  if (e == hipSuccess) e = hipMalloc(&ctx->t2_count, sizeof(unsigned int) * counts);
+  if (e != hipSuccess) {
+    (void)hipFree(ctx->t2_list);
+    (void)hipFree(ctx->t2_count);
+    ctx->t2_list = nullptr;
+    ctx->t2_count = nullptr;
+    return hip_fail(ctx, e, "second-tier workspace");
+  }
+  ctx->t2_slots = slots;
+  ctx->t2_counts = counts;
+  return AIR_OK;
 }
 
 bool prec_ok(air_prec p) { return p == AIR_FP64 || p == AIR_FP32 || p == AIR_BF16X3 || p == AIR_FP16X3; }
@@ -187,8 +230,8 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
   if (!prec_ok(prec)) return fail(ctx, AIR_E_INVAL, "unknown precision");
   for (int s = 0; s < S; ++s)
     if (!std::isfinite(snr_db[s])) return fail(ctx, AIR_E_INVAL, "SNR values must be finite");
-  if (prec == AIR_BF16X3 || prec == AIR_FP16X3)
-    return fail(ctx, AIR_E_UNSUPPORTED, "matrix-core precisions are not available in this build");
+  if (prec == AIR_FP16X3 && !c->f16_ok)
+    return fail(ctx, AIR_E_UNSUPPORTED, "constellation coordinates exceed the half-precision range");
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, AIR_E_DEVICE, "cannot select the context's device");
   if (!is_device_ptr(ctx, in)) return fail(ctx, AIR_E_INVAL, "input block is not device memory of this context");
@@ -198,8 +241,12 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
 
   const bool fp64 = prec == AIR_FP64;
   const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
-  const int grid = vec_grid(N);
-  const VecFn fn = fp64 ? kVecF64[c->D] : kVecF32[c->D];
+  // matrix-core tiles hold 16 or 32 points; smaller sets run the FP32 vector kernel
+  const bool mfma = (prec == AIR_FP16X3 || prec == AIR_BF16X3) && c->M >= 16;
+  const int grid = mfma ? mfma_grid(N) : vec_grid(N);
+  const VecFn vfn = fp64 ? kVecF64[c->D] : kVecF32[c->D];
+  const MfmaFn mfn = prec == AIR_BF16X3 ? kMfmaBF16[c->D] : kMfmaF16[c->D];
+  const void* rec = prec == AIR_BF16X3 ? (const void*)c->rec_bf16 : (const void*)c->rec_f16;
   DemapArgs a;
   std::memset(&a, 0, sizeof(a));
   a.in = in;
@@ -215,6 +262,20 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
   a.m = c->m;
   a.D = c->D;
   a.sweep = sweep;
+  if (mfma) {
+    // per (SNR point, wave) a run of list slots, one per sample tile the wave owns
+    const int64_t ntiles = (N + 31) / 32;
+    const int64_t waves = (int64_t)grid * 4;
+    const int64_t tpw = (ntiles + waves - 1) / waves;
+    if (ntiles >= ((int64_t)1 << 32)) return fail(ctx, AIR_E_UNSUPPORTED, "N too large for one call");
+    const int64_t sl = S < kMaxSnrPerLaunch ? S : kMaxSnrPerLaunch;
+    const air_status st = ensure_t2(ctx, sl * waves * tpw, sl * waves);
+    if (st != AIR_OK) return st;
+    a.t2_list = ctx->t2_list;
+    a.t2_count = ctx->t2_count;
+    a.t2_partials = ctx->t2_partials;
+    a.t2_tpw = (int)tpw;
+  }
   hipError_t e = hipMemsetAsync(ctx->call, 0, sizeof(CallWords), ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "clear call words");
   for (int s0 = 0; s0 < S; s0 += kMaxSnrPerLaunch) {
@@ -237,14 +298,15 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
       e = hipEventRecord(evp[0], ctx->stream);
       if (e != hipSuccess) return hip_fail(ctx, e, "timing event record");
     }
-    e = fn(a, grid, ctx->stream);
+    e = mfma ? mfn(a, rec, grid, ctx->stream) : vfn(a, grid, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "demapping kernel launch");
     if (evp) {
       e = hipEventRecord(evp[1], ctx->stream);
       if (e != hipSuccess) return hip_fail(ctx, e, "timing event record");
     }
-    hipLaunchKernelGGL(finish_kernel, dim3(ns), dim3(256), 0, ctx->stream, ctx->partials, grid, N,
-                       c->M, c->m, stats ? stats + 4 * s0 : nullptr, ctx->call, ctx->sticky);
+    hipLaunchKernelGGL(finish_kernel, dim3(ns), dim3(256), 0, ctx->stream, ctx->partials,
+                       mfma ? ctx->t2_partials : nullptr, grid, N, c->M, c->m,
+                       stats ? stats + 4 * s0 : nullptr, ctx->call, ctx->sticky);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "reduction kernel launch");
   }
@@ -268,6 +330,7 @@ air_status air_create(air_ctx** out, int device, void* hip_stream) {
     ctx->device = device;
     ctx->stream = (hipStream_t)hip_stream;
     hipError_t e = hipMalloc(&ctx->partials, sizeof(double) * kMaxGrid * kMaxSnrPerLaunch * 4);
+    if (e == hipSuccess) e = hipMalloc(&ctx->t2_partials, sizeof(double) * kMaxGrid * kMaxSnrPerLaunch * 4);
     if (e == hipSuccess) e = hipMalloc(&ctx->call, sizeof(CallWords));
     if (e == hipSuccess) e = hipMalloc(&ctx->sticky, sizeof(int));
     if (e == hipSuccess) e = hipMemset(ctx->call, 0, sizeof(CallWords));
@@ -291,6 +354,9 @@ void air_destroy(air_ctx* ctx) {
   (void)hipFree(ctx->partials);
   (void)hipFree(ctx->call);
   (void)hipFree(ctx->sticky);
+  (void)hipFree(ctx->t2_list);
+  (void)hipFree(ctx->t2_count);
+  (void)hipFree(ctx->t2_partials);
   for (hipEvent_t ev : ctx->ev) (void)hipEventDestroy(ev);
   delete ctx;
 }
@@ -358,6 +424,20 @@ air_status air_const_create(air_ctx* ctx, const double* X, const uint32_t* label
     }
     es /= (double)M;
     if (!(es > 0.0)) return fail(ctx, AIR_E_INVAL, "constellation has zero energy");
+    const int kp = 16 * mfma_nk(D);
+    std::vector<uint16_t> r16((size_t)M * kp), rbf((size_t)M * kp);
+    bool f16_ok = true;
+    for (int l = 0; l < M; ++l) {
+      double q = 0.0;
+      for (int d = 0; d < D; ++d) {
+        const double v = x64[(size_t)l * D + d];
+        q += v * v;
+        f16_ok &= std::fabs(v) < 60000.0;
+      }
+      f16_ok &= q < 60000.0;
+      point_record(&x64[(size_t)l * D], D, false, &r16[(size_t)l * kp]);
+      point_record(&x64[(size_t)l * D], D, true, &rbf[(size_t)l * kp]);
+    }
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, AIR_E_DEVICE, "cannot select the context's device");
     air_const* c = new air_const();
@@ -367,9 +447,14 @@ air_status air_const_create(air_ctx* ctx, const double* X, const uint32_t* label
     c->D = D;
     c->m = bits_of(M);
     c->es = es;
+    c->f16_ok = f16_ok;
     hipError_t e = hipMalloc(&c->x64, sizeof(double) * M * D);
     if (e == hipSuccess) e = hipMalloc(&c->x32, sizeof(float) * M * D);
     if (e == hipSuccess) e = hipMalloc(&c->lab, sizeof(uint32_t) * M);
+    if (e == hipSuccess) e = hipMalloc(&c->rec_f16, sizeof(uint16_t) * M * kp);
+    if (e == hipSuccess) e = hipMalloc(&c->rec_bf16, sizeof(uint16_t) * M * kp);
+    if (e == hipSuccess) e = hipMemcpy(c->rec_f16, r16.data(), sizeof(uint16_t) * M * kp, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->rec_bf16, rbf.data(), sizeof(uint16_t) * M * kp, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->x64, x64.data(), sizeof(double) * M * D, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->x32, x32.data(), sizeof(float) * M * D, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->lab, labels, sizeof(uint32_t) * M, hipMemcpyHostToDevice);
@@ -391,6 +476,8 @@ void air_const_destroy(air_const* c) {
   (void)hipFree(c->x64);
   (void)hipFree(c->x32);
   (void)hipFree(c->lab);
+  (void)hipFree(c->rec_f16);
+  (void)hipFree(c->rec_bf16);
   delete c;
 }
 

@@ -46,6 +46,11 @@ struct DemapArgs {
   int64_t llr_stride_s;             // elements between consecutive SNR planes of llr
   int M, m, D, S;
   int sweep;                        // 1: y = x_t + sigma_s z from `in`
+  // second tier of the matrix-core path (unused by the vector kernels)
+  unsigned long long* t2_list;      // [S][waves][tpw]: sample tile (32 bits) | lane mask (32)
+  unsigned int* t2_count;           // [S][waves]: tiles listed by each wave of the launch
+  double* t2_partials;              // [S][4][gridDim.x], as partials, from the second tier
+  int t2_tpw;                       // list slots per (SNR point, wave)
   SnrTable snr;
 };
 
@@ -170,13 +175,31 @@ __device__ __noinline__ T slow_rel(const T* __restrict__ in, int sweep, const T*
   return dmax + Real<T>::log2(sum);
 }
 
+// What the exact path needs of one call: where the sample's point comes from
+// and the constellation, with the SNR's scalars in the working type.
+template <typename T>
+struct ExactArgs {
+  const T* in;                      // received points, or unit noise in sweep mode
+  int sweep;
+  const T* xl;                      // label-ordered coordinates
+  int M, m;
+  T sigma, c;
+  unsigned long long* recomputed;   // count of items that took the exact path
+};
+
+template <typename T>
+__device__ __forceinline__ ExactArgs<T> exact_args(const DemapArgs& a, int s) {
+  return ExactArgs<T>{static_cast<const T*>(a.in), a.sweep, static_cast<const T*>(a.xl), a.M, a.m,
+                      Real<T>::sigma(a.snr, s), Real<T>::c(a.snr, s), a.recomputed};
+}
+
 // Outputs of one (sample, SNR) item from its fast-path sums.
 //  total:   sum_j 2^arg_j;  side[2k+b]: the same over bit side (k, b).
 //  arg_t:   arg of the transmitted point (used when tl >= 0).
 // Writes the m LLRs (if llr_out) and returns u, v through the references.
 // Entries below the starvation bound are recomputed exactly.
 template <typename T, int D>
-__device__ __forceinline__ void finish_item(const DemapArgs& a, int64_t n, int tl, int s,
+__device__ __forceinline__ void finish_item(const ExactArgs<T>& a, int64_t n, int tl,
                                             T total, const T (&side)[2 * kMaxBits], T arg_t,
                                             T* llr_out, T& u, T& v) {
   const int m = a.m;
@@ -199,9 +222,9 @@ __device__ __forceinline__ void finish_item(const DemapArgs& a, int64_t n, int t
     // total itself is starved every entry is (each side is below the total),
     // and all of them stay relative to a_r; otherwise the recomputed sides are
     // put back in the fast path's units by adding K + a_r, which is then small.
-    const T* in = static_cast<const T*>(a.in);
-    const T* xl = static_cast<const T*>(a.xl);
-    const T sigma = Real<T>::sigma(a.snr, s), c = Real<T>::c(a.snr, s);
+    const T* in = a.in;
+    const T* xl = a.xl;
+    const T sigma = a.sigma, c = a.c;
     atomicAdd(a.recomputed, 1ull);
     const int r = slow_nearest<T, D>(in, a.sweep, xl, a.M, sigma, n, tl);
     total_slow = !(total >= thr);

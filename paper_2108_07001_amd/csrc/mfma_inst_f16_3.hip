@@ -1,0 +1,15 @@
+// mfma_inst_f16_3.hip -- instances of the matrix-core demapping kernels
+// (half-precision splits, D = 13..16); split across files so that hipcc runs in parallel.
+#include "mfma_kernels.h"
+
+namespace air {
+#define AIR_MFMA_INST(D) \
+  hipError_t launch_mfma_f16_d##D(const DemapArgs& a, const void* rec, int g, hipStream_t s) { \
+    return launch_mfma_td<D, false>(a, rec, g, s); \
+  }
+AIR_MFMA_INST(13)
+AIR_MFMA_INST(14)
+AIR_MFMA_INST(15)
+AIR_MFMA_INST(16)
+#undef AIR_MFMA_INST
+}  // namespace air

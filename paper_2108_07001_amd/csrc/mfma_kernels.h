@@ -1,0 +1,700 @@
+// mfma_kernels.h -- matrix-core demapping kernels (AIR_FP16X3, AIR_BF16X3).
+//
+// The exponent tile arg[i][j] = K - c |y_j - x_i|^2 of 32 constellation points
+// (rows i) by 32 received samples (columns j) is one chain of
+// v_mfma_f32_32x32x16_{f16,bf16} products in the expanded form
+//
+//   arg = (2c y).x_i - c |x_i|^2 + (K - c |y|^2),
+//
+// with FP32 accumulation. Both factors of the two products are split into a
+// high and a low half-precision part, and three of the four cross products
+// are kept (hi*hi + hi*lo + lo*hi), which leaves a relative error of about
+// 2^-22 (f16) or 2^-16 (bf16) per term. The feature order along K is
+//   [w_hi.x_hi (D) | w_hi.x_lo (D) | w_lo.x_hi (D) | nc_hi q_hi, nc_hi q_lo, nc_lo q_hi | 0...]
+// with w = 2 c y, nc = -c, q = |x|^2; the point side of every K slot is a
+// precomputed record (16 bytes per lane-half per 16 K slots), the sample side
+// is formed in registers once per (sample, SNR). The per-sample constant
+// K - c|y|^2 enters as the accumulator input, so it costs no K slot.
+//
+// Layout of the 32x32 accumulator (measured on gfx950): lane l holds column
+// j = l % 32 (one sample) and rows r = 8 (e / 4) + 4 (l / 32) + e % 4 for its
+// 16 elements e. A 32-point tile holds the points whose labels are
+// 32 t + r, so label bits {0,1,3,4} are the element bits of e, bit 2 is the
+// lane half, and bits >= 5 are the tile index t. The bit-side sums are then
+// formed as in the vector kernels: R[e] accumulates over tiles, a
+// binary-counter tree over t feeds the high bits, and the two lane halves of
+// a sample exchange their partial sums once per (sample tile, SNR).
+//
+// The transmitted point's own term is taken from a second product whose A
+// rows are the 32 samples' transmitted points (the diagonal of that tile),
+// so u = log2 S - log2 e_t uses bit-for-bit the term that entered S.
+//
+// Two tiers. The main kernel sums the FP32 terms 2^arg with the fixed shift K
+// (window of ~150 nats of |LLR|). An item with a starved entry is left out of
+// the main kernel's sums; its tile is listed in the wave's own slots, and the
+// second-tier kernel -- launched with the same grid, each wave taking the
+// list of the same main-kernel wave in order -- re-forms those tiles' sums in
+// an FP64 frame, each term split as 2^frac(a) * 2^floor(a) (one exp2 in
+// [1, 2), one ldexp), which widens the window to ~700 nats. What is still
+// starved there takes the exact per-item path. Both kernels write per-block
+// partial sums in a fixed order, so every result is independent of timing.
+#pragma once
+#include "device_common.h"
+
+namespace air {
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float float16_t __attribute__((ext_vector_type(16)));
+
+constexpr int kTileLevels = kMaxBits - 5;   // label bits carried by the point-tile index
+
+// K slots used by a constellation of dimension D, padded to whole products.
+__host__ __device__ constexpr int mfma_nk(int D) { return (3 * D + 3 + 15) / 16; }
+
+template <bool BF> struct MfmaOp;
+template <> struct MfmaOp<false> {
+  typedef half8_t vec;
+  typedef _Float16 elem;
+  static __device__ __forceinline__ float16_t mma(vec a, vec b, float16_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct MfmaOp<true> {
+  typedef bf16x8_t vec;
+  typedef __bf16 elem;
+  static __device__ __forceinline__ float16_t mma(vec a, vec b, float16_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+// hi + lo split of an FP32 value in the operand type (round to nearest even).
+template <bool BF>
+__device__ __forceinline__ void split2(float v, typename MfmaOp<BF>::elem& hi,
+                                       typename MfmaOp<BF>::elem& lo) {
+  typedef typename MfmaOp<BF>::elem E;
+  hi = (E)v;
+  lo = (E)(v - (float)hi);
+}
+
+// The two values a lane pair (l, l + 32) holds: lo from lane l, hi from lane
+// l + 32, the same in both lanes (v_permlane32_swap, no LDS round trip).
+__device__ __forceinline__ void halves(float v, float& lo, float& hi) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  lo = __uint_as_float(r[0]);
+  hi = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void halves(double v, double& lo, double& hi) {
+  const uint64_t b = __double_as_longlong(v);
+  const auto r0 = __builtin_amdgcn_permlane32_swap((uint32_t)b, (uint32_t)b, false, false);
+  const auto r1 = __builtin_amdgcn_permlane32_swap((uint32_t)(b >> 32), (uint32_t)(b >> 32), false, false);
+  lo = __longlong_as_double((long long)(((uint64_t)r1[0] << 32) | r0[0]));
+  hi = __longlong_as_double((long long)(((uint64_t)r1[1] << 32) | r0[1]));
+}
+// Sum of the two halves' values, bitwise identical in both lanes of the pair.
+template <typename F>
+__device__ __forceinline__ F pair_sum(F v) {
+  F lo, hi;
+  halves(v, lo, hi);
+  return lo + hi;
+}
+
+// Constellation tables a kernel reads per sample: labels of point indices,
+// label-ordered FP32 coordinates and the matrix-core point records. They are
+// either the global copies or block-local LDS copies.
+template <bool BF>
+struct Tables {
+  const uint32_t* lab;
+  const float* xl;
+  const typename MfmaOp<BF>::vec* rec;
+};
+
+// One block of samples at one SNR point: where the samples come from, the
+// constellation size and the SNR's scalars (a launch of the sweep or a job of
+// the serving loop).
+struct SampleParams {
+  const float* in;          // N x D received points, or unit noise in sweep mode
+  const uint32_t* tx;       // N transmitted indices, or nullptr
+  int64_t N;
+  int M, m, sweep;
+  float c, sigma;
+  int* err;                 // set when a transmitted index is out of range
+};
+
+__device__ __forceinline__ SampleParams sample_params(const DemapArgs& a, int s) {
+  return SampleParams{static_cast<const float*>(a.in), a.tx, a.N, a.M, a.m, a.sweep,
+                      a.snr.cf[s], a.snr.sigmaf[s], a.err};
+}
+
+// Raw inputs of this lane's sample in one tile, loaded ahead of use: the
+// transmitted label and point, and the unit noise (or received point).
+template <int D>
+struct TileInput {
+  uint32_t t;          // transmitted index as given (validated in setup)
+  int tl;              // its label, or 0 when not available
+  float z[D];
+  float xt[D];         // coordinates of the transmitted point (sweep mode)
+  template <bool BF>
+  __device__ __forceinline__ void load(const SampleParams& p, const Tables<BF>& tb, int64_t st, int j) {
+    const int64_t n = st * 32 + j;
+    const bool valid = n < p.N;
+    t = (valid && p.tx) ? p.tx[n] : 0u;
+    const float* __restrict__ in = p.in + n * D;
+#pragma unroll
+    for (int d = 0; d < D; ++d) z[d] = valid ? in[d] : 0.0f;
+    tl = (t < (uint32_t)p.M) ? (int)tb.lab[t] : 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) xt[d] = p.sweep ? tb.xl[tl * D + d] : 0.0f;
+  }
+};
+
+// One 32-sample tile at one SNR point: the received points, the sample-side
+// operands and the accumulator input of this lane's sample.
+template <int D, bool BF>
+struct SampleTile {
+  typedef typename MfmaOp<BF>::vec V;
+  typedef typename MfmaOp<BF>::elem E;
+  static constexpr int NK = mfma_nk(D);
+  static constexpr int KP = 16 * NK;
+  int64_t n;
+  bool valid, live;
+  int tl, tq;          // label of the transmitted point (-1 none, -2 invalid); in-bounds row
+  bool ovf;            // sample side outside the f16 range: exact path
+  V B[NK];
+  float16_t cinit;
+
+  __device__ __forceinline__ void setup(const SampleParams& p, int64_t st, int j, int h,
+                                        bool flag_errors, const TileInput<D>& ti) {
+    const int M = p.M;
+    n = st * 32 + j;
+    valid = n < p.N;
+    tl = -1;
+    if (valid && p.tx) {
+      if (ti.t >= (uint32_t)M) {
+        if (flag_errors && h == 0) atomicOr(p.err, 1);
+        tl = -2;
+      } else {
+        tl = ti.tl;
+      }
+    }
+    live = valid && tl != -2;
+    tq = tl >= 0 ? tl : 0;
+    const float c = p.c;
+    const float sigma = p.sigma;
+    const float K = Real<float>::shift(p.m);
+    float y[D];
+    float yy = 0.0f;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const float zi = live ? ti.z[d] : 0.0f;
+      y[d] = (p.sweep && live) ? __builtin_fmaf(sigma, zi, ti.xt[d]) : zi;
+      yy = __builtin_fmaf(y[d], y[d], yy);
+    }
+    // sample-side features; each lane takes its half of every 16-slot group,
+    // selected on packed 32-bit words so the choice never becomes an index
+    E F[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) F[k] = (E)0.0f;
+    ovf = !(c < 60000.0f);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const float w = 2.0f * c * y[d];
+      ovf |= !(__builtin_fabsf(w) < 60000.0f);
+      E hi, lo;
+      split2<BF>(w, hi, lo);
+      F[d] = hi;
+      F[D + d] = hi;
+      F[2 * D + d] = lo;
+    }
+    if (BF) ovf = false;  // bfloat16 has the FP32 range
+    {
+      E hi, lo;
+      split2<BF>(-c, hi, lo);
+      F[3 * D] = hi;
+      F[3 * D + 1] = hi;
+      F[3 * D + 2] = lo;
+    }
+    const uint32_t hmask = 0u - (uint32_t)h;
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+      uint32_t wd[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint32_t w0, w1;
+        E p0[2] = {F[16 * kk + 2 * q], F[16 * kk + 2 * q + 1]};
+        E p1[2] = {F[16 * kk + 8 + 2 * q], F[16 * kk + 8 + 2 * q + 1]};
+        __builtin_memcpy(&w0, p0, 4);
+        __builtin_memcpy(&w1, p1, 4);
+        wd[q] = (w0 & ~hmask) | (w1 & hmask);
+      }
+      __builtin_memcpy(&B[kk], wd, 16);
+    }
+    const float c0 = __builtin_fmaf(-c, yy, K);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) cinit[e] = c0;
+  }
+
+  __device__ __forceinline__ float16_t product(const V (&A)[NK]) const {
+    float16_t acc = MfmaOp<BF>::mma(A[0], B[0], cinit);
+#pragma unroll
+    for (int kk = 1; kk < NK; ++kk) acc = MfmaOp<BF>::mma(A[kk], B[kk], acc);
+    return acc;
+  }
+
+  // arg of the sample's own transmitted point: the diagonal of the product
+  // whose A rows are the 32 samples' transmitted points. Row j of column j
+  // sits in lane half (j >> 2) & 1, element (j & 3) | ((j >> 3) << 2).
+  __device__ __forceinline__ float transmitted_arg(const V* __restrict__ rec, int j, int h) const {
+    V At[NK];
+    const V* rp = rec + ((int64_t)tq * NK) * 2 + h;
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) At[kk] = rp[2 * kk];
+    const float16_t acc = product(At);
+    // element (j & 3) | ((j >> 3) << 2), picked by a tree over its four bits;
+    // bitwise selects keep the choice from turning into an indexed access
+    auto pick = [](float a, float b, uint32_t mask) {
+      return __builtin_bit_cast(float, (__builtin_bit_cast(uint32_t, a) & ~mask) |
+                                           (__builtin_bit_cast(uint32_t, b) & mask));
+    };
+    const uint32_t m0 = 0u - (uint32_t)(j & 1), m1 = 0u - (uint32_t)((j >> 1) & 1);
+    const uint32_t m2 = 0u - (uint32_t)((j >> 3) & 1), m3 = 0u - (uint32_t)((j >> 4) & 1);
+    float v8[8], v4[4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v8[i] = pick(acc[2 * i], acc[2 * i + 1], m0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v4[i] = pick(v8[2 * i], v8[2 * i + 1], m1);
+    const float mine = pick(pick(v4[0], v4[1], m2), pick(v4[2], v4[3], m2), m3);
+    float lo, hi;
+    halves(mine, lo, hi);
+    return ((j >> 2) & 1) ? hi : lo;
+  }
+};
+
+// Running bit-side sums of one lane over the point tiles (type F: float or double).
+template <typename F, int NE>
+struct TileSums {
+  F R[NE];
+  F g0[kTileLevels], g1[kTileLevels], gn[kTileLevels];
+  F tot;
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int l = 0; l < kTileLevels; ++l) { g0[l] = 0; g1[l] = 0; gn[l] = 0; }
+    tot = 0;
+  }
+  // add the NE terms of tile t (consumes ev)
+  __device__ __forceinline__ void add(F (&ev)[NE], int t, int ntb) {
+    if (t == 0) {
+#pragma unroll
+      for (int e = 0; e < NE; ++e) R[e] = ev[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < NE; ++e) R[e] += ev[e];
+    }
+#pragma unroll
+    for (int w2 = NE / 2; w2 >= 1; w2 >>= 1)
+#pragma unroll
+      for (int e = 0; e < w2; ++e) ev[e] = ev[2 * e] + ev[2 * e + 1];
+    F carry = ev[0];
+    bool placed = false;
+#pragma unroll
+    for (int l = 0; l < kTileLevels; ++l) {
+      if (!placed && l < ntb) {
+        if ((t >> l) & 1) {
+          g0[l] += gn[l];
+          g1[l] += carry;
+          carry = gn[l] + carry;
+        } else {
+          gn[l] = carry;
+          placed = true;
+        }
+      }
+    }
+    if (!placed) tot = carry;
+  }
+  // Combine with the other lane half of the sample: side[2k + b] and total,
+  // identical in both halves (a + b in one, b + a in the other).
+  __device__ __forceinline__ void combine(int ntb, F (&side)[2 * kMaxBits], F& total) const {
+    constexpr int NEB = NE == 8 ? 3 : 4;
+#pragma unroll
+    for (int i = 0; i < 2 * kMaxBits; ++i) side[i] = 0;
+    // pairwise fold of R over the element bits; label bits 0, 1, 3, 4 <- element bits 0..3
+    F cur[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) cur[e] = R[e];
+#pragma unroll
+    for (int eb = 0; eb < NEB; ++eb) {
+      const int half = NE >> (eb + 1);   // pairs left at this level
+      F a0 = cur[0], a1 = cur[1];
+#pragma unroll
+      for (int i = 1; i < NE / 2; ++i)
+        if (i < half) {
+          a0 += cur[2 * i];
+          a1 += cur[2 * i + 1];
+        }
+#pragma unroll
+      for (int i = 0; i < NE / 2; ++i)
+        if (i < half) cur[i] = cur[2 * i] + cur[2 * i + 1];
+      const int k = eb < 2 ? eb : eb + 1;
+      side[2 * k] = pair_sum(a0);
+      side[2 * k + 1] = pair_sum(a1);
+    }
+    F lo, hi;
+    halves(tot, lo, hi);
+    side[4] = lo;               // label bit 2 = lane half
+    side[5] = hi;
+    total = lo + hi;
+#pragma unroll
+    for (int l = 0; l < kTileLevels; ++l)
+      if (l < ntb) {
+        side[2 * (5 + l)] = pair_sum(g0[l]);
+        side[2 * (5 + l) + 1] = pair_sum(g1[l]);
+      }
+  }
+};
+
+// Record pointer of point row `t * 32 + j` for this lane half. Rows 16..31 of
+// a 16-point set land only in elements e >= 8, which are not used; they read
+// a valid record (row j - 16) to stay in bounds.
+template <bool BF, bool HALF, int NK>
+__device__ __forceinline__ const typename MfmaOp<BF>::vec* rec_row(const typename MfmaOp<BF>::vec* rec,
+                                                                   int t, int j, int h) {
+  const int prow = HALF ? (j & 15) : t * 32 + j;
+  return rec + ((int64_t)prow * NK) * 2 + h;
+}
+
+// Bytes of the block-local copies of the constellation tables.
+__host__ __device__ constexpr int64_t table_bytes(int M, int D) {
+  return (int64_t)M * 4 + (int64_t)M * D * 4 + 16 + (int64_t)M * mfma_nk(D) * 32;
+}
+
+// First tier of one sample tile: all point tiles through the matrix cores,
+// FP32 terms 2^(a_j + K), bit-side sums, then this lane half's LLRs (bits
+// k = h mod 2) and the sample's MI/GMI terms u, v. need2 is set when an entry
+// is below the starvation bound (the item then belongs to the second tier and
+// u, v are not final).
+template <int D, bool BF, bool HALF>
+__device__ __forceinline__ void tier1_tile(const SampleTile<D, BF>& smp, const Tables<BF>& tb,
+                                           bool has_tx, int j, int h, int m, int NT, int ntb,
+                                           float thr, float* lout, float& u, float& v,
+                                           bool& need2) {
+  typedef typename MfmaOp<BF>::vec V;
+  constexpr int NK = SampleTile<D, BF>::NK;
+  constexpr int NE = HALF ? 8 : 16;
+  // point tiles: the next tile's records load while this one's exp2 and sums
+  // run (other waves on the SIMD cover the product latency)
+  TileSums<float, NE> ts;
+  ts.init();
+  {
+    V A[NK];
+    const V* rp = rec_row<BF, HALF, NK>(tb.rec, 0, j, h);
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) A[kk] = rp[2 * kk];
+    for (int t = 0; t < NT; ++t) {
+      const float16_t acc = smp.product(A);
+      if (t + 1 < NT) {
+        const V* rq = rec_row<BF, HALF, NK>(tb.rec, t + 1, j, h);
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) A[kk] = rq[2 * kk];
+      }
+      float ev[NE];
+#pragma unroll
+      for (int e = 0; e < NE; ++e) ev[e] = Real<float>::exp2(acc[e]);
+      ts.add(ev, t, ntb);
+    }
+  }
+  const float arg_t = has_tx ? smp.transmitted_arg(tb.rec, j, h) : 0.f;
+  float side[2 * kMaxBits];
+  float total;
+  ts.combine(ntb, side, total);
+
+  bool starved = smp.ovf || !(total >= thr);
+#pragma unroll
+  for (int i = 0; i < 2 * kMaxBits; ++i)
+    if (i < 2 * m) starved |= !(side[i] >= thr);
+  u = 0.f;
+  v = 0.f;
+  if (smp.live && !starved) {
+    const float lam_tot = Real<float>::log2(total);
+    float vpart = 0.f;
+#pragma unroll
+    for (int i = 0; i < kMaxBits / 2; ++i) {
+      const int k = 2 * i + h;
+      if (k < m) {
+        const float s0 = h ? side[4 * i + 2] : side[4 * i];
+        const float s1 = h ? side[4 * i + 3] : side[4 * i + 1];
+        const float l0 = Real<float>::log2(s0), l1 = Real<float>::log2(s1);
+        if (lout) lout[k] = Real<float>::ln2() * (l0 - l1);
+        if (smp.tl >= 0) vpart += lam_tot - (((smp.tl >> k) & 1) ? l1 : l0);
+      }
+    }
+    v = pair_sum(vpart);
+    u = lam_tot - Real<float>::log2(Real<float>::exp2(arg_t));
+  }
+  need2 = smp.live && starved;
+  // an invalid transmitted index leaves the sample's LLRs undefined
+  if (smp.valid && !smp.live && lout && h == 0)
+    for (int k = 0; k < m; ++k) lout[k] = Real<float>::nan();
+}
+
+// Second tier of one listed sample tile: the terms re-formed in an FP64 frame
+// 2^(a + K64), K64 = 1022 - m, built exactly from one FP32 exp2 of the
+// fractional part and an ldexp by the integer part. Lanes whose sample is
+// flagged finish it here, or on the exact path when even this frame starves
+// (or the sample side left the f16 range).
+template <int D, bool BF, bool HALF>
+__device__ __forceinline__ void tier2_tile(const SampleTile<D, BF>& smp, const Tables<BF>& tb,
+                                           const ExactArgs<float>& ex, bool has_tx, bool flagged,
+                                           int j, int h, int m, int NT, int ntb, float* lout,
+                                           float& u, float& v) {
+  typedef typename MfmaOp<BF>::vec V;
+  constexpr int NK = SampleTile<D, BF>::NK;
+  constexpr int NE = HALF ? 8 : 16;
+  const float K = Real<float>::shift(m);
+  const int K64 = 1022 - m;
+  const double thr64 = __builtin_ldexp(1.0, m - 1022 + 60);
+  auto val64 = [&](float x) -> double {
+    const float ap = x - K;                         // a_j in log2 units (<= 0)
+    const float fr = __builtin_amdgcn_fractf(ap);   // ap - floor(ap), in [0, 1)
+    const int ni = (int)(ap - fr);
+    return __builtin_ldexp((double)Real<float>::exp2(fr), ni + K64);
+  };
+  TileSums<double, NE> ts;
+  ts.init();
+  {
+    V A[NK];
+    const V* rp = rec_row<BF, HALF, NK>(tb.rec, 0, j, h);
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) A[kk] = rp[2 * kk];
+    for (int t = 0; t < NT; ++t) {
+      const float16_t acc = smp.product(A);
+      if (t + 1 < NT) {
+        const V* rq = rec_row<BF, HALF, NK>(tb.rec, t + 1, j, h);
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) A[kk] = rq[2 * kk];
+      }
+      double ev[NE];
+#pragma unroll
+      for (int e = 0; e < NE; ++e) ev[e] = val64(acc[e]);
+      ts.add(ev, t, ntb);
+    }
+  }
+  const float arg_t = has_tx ? smp.transmitted_arg(tb.rec, j, h) : 0.f;
+  double side[2 * kMaxBits];
+  double total;
+  ts.combine(ntb, side, total);
+
+  bool st2 = smp.ovf || !(total >= thr64);
+#pragma unroll
+  for (int i = 0; i < 2 * kMaxBits; ++i)
+    if (i < 2 * m) st2 |= !(side[i] >= thr64);
+  u = 0.f;
+  v = 0.f;
+  if (flagged && !st2) {
+    const double lt = ::log2(total);
+    double vpart = 0.0;
+#pragma unroll
+    for (int i = 0; i < kMaxBits / 2; ++i) {
+      const int k = 2 * i + h;
+      if (k < m) {
+        const double l0 = ::log2(h ? side[4 * i + 2] : side[4 * i]);
+        const double l1 = ::log2(h ? side[4 * i + 3] : side[4 * i + 1]);
+        if (lout) lout[k] = (float)(0.6931471805599453094 * (l0 - l1));
+        if (smp.tl >= 0) vpart += lt - (((smp.tl >> k) & 1) ? l1 : l0);
+      }
+    }
+    v = (float)pair_sum(vpart);
+    u = (float)(lt - ::log2(val64(arg_t)));
+    if (h == 0) atomicAdd(ex.recomputed, 1ull);
+  }
+  // beyond the FP64 window, or a sample side outside the f16 range: exact path
+  if (flagged && st2 && h == 0) {
+    float zside[2 * kMaxBits];
+#pragma unroll
+    for (int i = 0; i < 2 * kMaxBits; ++i) zside[i] = 0.f;
+    finish_item<float, D>(ex, smp.n, smp.tl, 0.f, zside, arg_t, lout, u, v);
+  }
+}
+
+template <int D, bool BF, bool HALF, bool TBL>
+__global__ __launch_bounds__(256) void demap_mfma(const DemapArgs a,
+                                                  const typename MfmaOp<BF>::vec* __restrict__ rec,
+                                                  const float* __restrict__ xl) {
+  typedef typename MfmaOp<BF>::vec V;
+  typedef SampleTile<D, BF> ST;
+  constexpr int NK = ST::NK;
+  extern __shared__ double acc_lds[];      // [waves][S][4], then the tables (TBL)
+  const int lane = threadIdx.x & 63;
+  const int h = lane >> 5;                 // lane half: label bit 2 of the rows held
+  const int j = lane & 31;                 // sample column within the tile
+  const int wave = threadIdx.x >> 6;
+  const int waves = blockDim.x >> 6;
+  const int S = a.S;
+  Tables<BF> tb{a.lab, xl, rec};
+  if (TBL) {
+    // small constellations: labels, coordinates and point records in LDS
+    const int M = a.M;
+    // byte offsets from the LDS base (integer arithmetic on the offsets, not
+    // on the pointers, so that the accesses stay recognisably LDS accesses)
+    char* lds = reinterpret_cast<char*>(acc_lds);
+    const int o_lab = waves * S * 4 * (int)sizeof(double);
+    const int o_xl = o_lab + M * 4;
+    const int o_rec = (o_xl + M * D * 4 + 15) & ~15;
+    uint32_t* l_lab = reinterpret_cast<uint32_t*>(lds + o_lab);
+    float* l_xl = reinterpret_cast<float*>(lds + o_xl);
+    V* l_rec = reinterpret_cast<V*>(lds + o_rec);
+    for (int i = threadIdx.x; i < M; i += blockDim.x) l_lab[i] = a.lab[i];
+    for (int i = threadIdx.x; i < M * D; i += blockDim.x) l_xl[i] = xl[i];
+    for (int i = threadIdx.x; i < M * NK * 2; i += blockDim.x) l_rec[i] = rec[i];
+    __syncthreads();
+    tb = Tables<BF>{l_lab, l_xl, l_rec};
+  }
+  const int m = a.m;
+  const int NT = HALF ? 1 : (a.M >> 5);
+  const int ntb = HALF ? 0 : m - 5;
+  const float thr = Real<float>::starve(m);
+  float* __restrict__ llr = static_cast<float*>(a.llr);
+  const int64_t ntiles = (a.N + 31) >> 5;
+  const int64_t wstride = (int64_t)gridDim.x * waves;
+  const int64_t wgid = (int64_t)blockIdx.x * waves + wave;
+
+  // The SNR loop is outermost: each lane keeps its FP64 sums for one SNR point
+  // over all of its wave's sample tiles, and the wave reduces them once.
+  for (int s = 0; s < S; ++s) {
+    double au = 0.0, av = 0.0, auu = 0.0, avv = 0.0;
+    unsigned long long* slots = a.t2_list + ((int64_t)s * wstride + wgid) * a.t2_tpw;
+    int nlisted = 0;
+    const SampleParams sp = sample_params(a, s);
+    TileInput<D> cur, nxt;
+    if (wgid < ntiles) cur.load(sp, tb, wgid, j);
+    for (int64_t st = wgid; st < ntiles; st += wstride) {
+      if (st + wstride < ntiles) nxt.load(sp, tb, st + wstride, j);   // next tile's inputs, ahead of use
+      ST smp;
+      smp.setup(sp, st, j, h, s == 0, cur);
+      cur = nxt;
+
+      float* lout = (llr && smp.valid) ? llr + (int64_t)s * a.llr_stride_s + smp.n * m : nullptr;
+      float u, v;
+      bool need2;
+      tier1_tile<D, BF, HALF>(smp, tb, a.tx != nullptr, j, h, m, NT, ntb, thr, lout, u, v, need2);
+      // items with a starved entry are finished by the second tier; their
+      // tile is listed once for this SNR point with the mask of such lanes
+      const unsigned long long fm = __ballot(need2 && h == 0) & 0xffffffffull;
+      if (fm != 0) {
+        if (lane == 0) slots[nlisted] = (fm << 32) | (unsigned long long)st;
+        ++nlisted;
+      }
+      if (h == 0 && smp.live && smp.tl >= 0 && !need2) {
+        const double du = (double)u, dv = (double)v;
+        au += du;
+        av += dv;
+        auu = __builtin_fma(du, du, auu);
+        avv = __builtin_fma(dv, dv, avv);
+      }
+    }
+    if (lane == 0) a.t2_count[(int64_t)s * wstride + wgid] = (unsigned int)nlisted;
+    const double w0 = wave_sum(au), w1 = wave_sum(av);
+    const double w2 = wave_sum(auu), w3 = wave_sum(avv);
+    if (lane == 0) {
+      double* acc = acc_lds + ((int64_t)wave * S + s) * 4;
+      acc[0] = w0;
+      acc[1] = w1;
+      acc[2] = w2;
+      acc[3] = w3;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < S * 4; i += blockDim.x) {
+    double t = 0.0;
+    for (int w = 0; w < waves; ++w) t += acc_lds[w * S * 4 + i];
+    a.partials[(int64_t)i * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// Second tier: every listed (SNR, sample tile) is re-formed in the FP64 frame.
+template <int D, bool BF, bool HALF>
+__global__ __launch_bounds__(256) void demap_mfma_t2(const DemapArgs a,
+                                                     const typename MfmaOp<BF>::vec* __restrict__ rec,
+                                                     const float* __restrict__ xl) {
+  typedef SampleTile<D, BF> ST;
+  extern __shared__ double acc_lds[];      // [waves][S][4]
+  const int lane = threadIdx.x & 63;
+  const int h = lane >> 5;
+  const int j = lane & 31;
+  const int wave = threadIdx.x >> 6;
+  const int waves = blockDim.x >> 6;
+  const int S = a.S;
+  const int m = a.m;
+  const int NT = HALF ? 1 : (a.M >> 5);
+  const int ntb = HALF ? 0 : m - 5;
+  float* __restrict__ llr = static_cast<float*>(a.llr);
+  const int64_t wstride = (int64_t)gridDim.x * waves;
+  const int64_t wgid = (int64_t)blockIdx.x * waves + wave;
+  const Tables<BF> tb{a.lab, xl, rec};
+
+  for (int s = 0; s < S; ++s) {
+    double au = 0.0, av = 0.0, auu = 0.0, avv = 0.0;
+    const unsigned long long* slots = a.t2_list + ((int64_t)s * wstride + wgid) * a.t2_tpw;
+    const int nlisted = (int)a.t2_count[(int64_t)s * wstride + wgid];
+    for (int q = 0; q < nlisted; ++q) {
+      const unsigned long long ent = slots[q];
+      const int64_t st = (int64_t)(ent & 0xffffffffull);
+      const uint32_t mask = (uint32_t)(ent >> 32);
+      const SampleParams sp = sample_params(a, s);
+      TileInput<D> ti;
+      ti.load(sp, tb, st, j);
+      ST smp;
+      smp.setup(sp, st, j, h, false, ti);
+
+      const bool flagged = (mask >> j) & 1u;
+      float* lout = (llr && smp.valid) ? llr + (int64_t)s * a.llr_stride_s + smp.n * m : nullptr;
+      float u, v;
+      tier2_tile<D, BF, HALF>(smp, tb, exact_args<float>(a, s), a.tx != nullptr, flagged, j, h, m,
+                              NT, ntb, lout, u, v);
+      if (flagged && h == 0 && smp.tl >= 0) {
+        const double du = (double)u, dv = (double)v;
+        au += du;
+        av += dv;
+        auu = __builtin_fma(du, du, auu);
+        avv = __builtin_fma(dv, dv, avv);
+      }
+    }
+    const double w0 = wave_sum(au), w1 = wave_sum(av);
+    const double w2 = wave_sum(auu), w3 = wave_sum(avv);
+    if (lane == 0) {
+      double* acc = acc_lds + ((int64_t)wave * S + s) * 4;
+      acc[0] = w0;
+      acc[1] = w1;
+      acc[2] = w2;
+      acc[3] = w3;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < S * 4; i += blockDim.x) {
+    double t = 0.0;
+    for (int w = 0; w < waves; ++w) t += acc_lds[w * S * 4 + i];
+    a.t2_partials[(int64_t)i * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+template <int D, bool BF>
+hipError_t launch_mfma_td(const DemapArgs& a, const void* rec, int grid, hipStream_t st) {
+  const size_t acc = sizeof(double) * 4 * a.S * 4;
+  const int64_t tbytes = table_bytes(a.M, D);
+  const bool tbl = tbytes <= 40 * 1024;
+  typedef typename MfmaOp<BF>::vec V;
+  const V* r = static_cast<const V*>(rec);
+  const float* x = static_cast<const float*>(a.xl);
+  if (a.M == 16) {
+    hipLaunchKernelGGL((demap_mfma<D, BF, true, true>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
+    hipLaunchKernelGGL((demap_mfma_t2<D, BF, true>), dim3(grid), dim3(256), acc, st, a, r, x);
+  } else {
+    if (tbl)
+      hipLaunchKernelGGL((demap_mfma<D, BF, false, true>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
+    else
+      hipLaunchKernelGGL((demap_mfma<D, BF, false, false>), dim3(grid), dim3(256), acc, st, a, r, x);
+    hipLaunchKernelGGL((demap_mfma_t2<D, BF, false>), dim3(grid), dim3(256), acc, st, a, r, x);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace air

@@ -1,0 +1,16 @@
+// serve_inst_f16_0.hip -- instances of the batched serving kernels
+// (half-precision splits, D = 1..4); split across files so that hipcc runs in parallel.
+#include "serve_kernels.h"
+
+namespace air {
+#define AIR_SERVE_INST(D)                                                                       \
+  hipError_t launch_serve_f16_d##D(const JobDesc* j, int n, int64_t items, bool half, int g, \
+                                   hipStream_t s) {                                            \
+    return launch_serve_td<D, false>(j, n, items, half, g, s);                                  \
+  }
+AIR_SERVE_INST(1)
+AIR_SERVE_INST(2)
+AIR_SERVE_INST(3)
+AIR_SERVE_INST(4)
+#undef AIR_SERVE_INST
+}  // namespace air

@@ -1,0 +1,16 @@
+// serve_inst_f16_3.hip -- instances of the batched serving kernels
+// (half-precision splits, D = 13..16); split across files so that hipcc runs in parallel.
+#include "serve_kernels.h"
+
+namespace air {
+#define AIR_SERVE_INST(D)                                                                       \
+  hipError_t launch_serve_f16_d##D(const JobDesc* j, int n, int64_t items, bool half, int g, \
+                                   hipStream_t s) {                                            \
+    return launch_serve_td<D, false>(j, n, items, half, g, s);                                  \
+  }
+AIR_SERVE_INST(13)
+AIR_SERVE_INST(14)
+AIR_SERVE_INST(15)
+AIR_SERVE_INST(16)
+#undef AIR_SERVE_INST
+}  // namespace air

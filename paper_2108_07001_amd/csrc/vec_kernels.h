@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void demap_vec(const DemapArgs a, const T* 
         T arg_t = 0;
         if (tl >= 0) arg_t = Real<T>::fma(-c, sqdist<T, D>(y, xl + (int64_t)tl * D), K);
         T u = 0, v = 0;
-        finish_item<T, D>(a, n, tl, s, total, side, arg_t, lout, u, v);
+        finish_item<T, D>(exact_args<T>(a, s), n, tl, total, side, arg_t, lout, u, v);
         if (tl >= 0) {
           su = (double)u;
           sv = (double)v;
