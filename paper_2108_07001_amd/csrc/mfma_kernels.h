@@ -134,17 +134,32 @@ struct TileInput {
   int tl;              // its label, or 0 when not available
   float z[D];
   float xt[D];         // coordinates of the transmitted point (sweep mode)
-  template <bool BF>
-  __device__ __forceinline__ void load(const SampleParams& p, const Tables<BF>& tb, int64_t st, int j) {
+  // global loads only (issued a tile ahead of use) ... They are made
+  // unconditional (a clamped row, a stand-in buffer when there is no tx) and
+  // their values are not masked here, so that no branch separates the loads
+  // from their use and the wait for them can count outstanding loads instead
+  // of draining all of them. setup() uses t and z only for valid samples (and
+  // t only when there are transmitted indices).
+  __device__ __forceinline__ void fetch(const SampleParams& p, int64_t st, int j) {
     const int64_t n = st * 32 + j;
-    const bool valid = n < p.N;
-    t = (valid && p.tx) ? p.tx[n] : 0u;
-    const float* __restrict__ in = p.in + n * D;
+    const int64_t nc = n < p.N ? n : p.N - 1;
+    const uint32_t* __restrict__ txp = p.tx ? p.tx : reinterpret_cast<const uint32_t*>(p.in);
+    t = txp[nc];
+    const float* __restrict__ in = p.in + nc * D;
 #pragma unroll
-    for (int d = 0; d < D; ++d) z[d] = valid ? in[d] : 0.0f;
+    for (int d = 0; d < D; ++d) z[d] = in[d];
+  }
+  // ... and the table lookups that depend on them, at the time of use
+  template <bool BF>
+  __device__ __forceinline__ void resolve(const SampleParams& p, const Tables<BF>& tb) {
     tl = (t < (uint32_t)p.M) ? (int)tb.lab[t] : 0;
 #pragma unroll
     for (int d = 0; d < D; ++d) xt[d] = p.sweep ? tb.xl[tl * D + d] : 0.0f;
+  }
+  template <bool BF>
+  __device__ __forceinline__ void load(const SampleParams& p, const Tables<BF>& tb, int64_t st, int j) {
+    fetch(p, st, j);
+    resolve(p, tb);
   }
 };
 
@@ -565,9 +580,11 @@ __global__ __launch_bounds__(256) void demap_mfma(const DemapArgs a,
     int nlisted = 0;
     const SampleParams sp = sample_params(a, s);
     TileInput<D> cur, nxt;
-    if (wgid < ntiles) cur.load(sp, tb, wgid, j);
+    if (wgid < ntiles) cur.fetch(sp, wgid, j);
     for (int64_t st = wgid; st < ntiles; st += wstride) {
-      if (st + wstride < ntiles) nxt.load(sp, tb, st + wstride, j);   // next tile's inputs, ahead of use
+      // next tile's inputs, ahead of use (the last round re-reads the last tile)
+      nxt.fetch(sp, st + wstride < ntiles ? st + wstride : ntiles - 1, j);
+      cur.resolve(sp, tb);
       ST smp;
       smp.setup(sp, st, j, h, s == 0, cur);
       cur = nxt;
