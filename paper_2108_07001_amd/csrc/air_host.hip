@@ -4,7 +4,7 @@
 #include "../../include/air.h"
 #include "device_common.h"
 #include "host_state.h"
-#include "mfma_kernels.h"
+#include "mfma_wide.h"
 
 #include <cmath>
 #include <cstring>
@@ -65,10 +65,11 @@ static const MfmaFn kMfmaBF16[kMaxD + 1] = {
     AIR_FN(bf16, 16)};
 #undef AIR_FN
 
-// Grid of a matrix-core launch: 4 waves per block, one 32-sample tile per wave and round.
+// Grid of a matrix-core launch: 4 waves per block, one pair of 32-sample
+// tiles (64 samples) per wave and round.
 static int mfma_grid(int64_t N) {
-  int64_t tiles = (N + 31) / 32;
-  int64_t g = (tiles + 3) / 4;
+  const int64_t pairs = ((N + 31) / 32 + 1) / 2;
+  const int64_t g = (pairs + 3) / 4;
   return (int)(g < kMaxGrid ? g : kMaxGrid);
 }
 
@@ -84,17 +85,19 @@ static int vec_grid(int64_t N) {
 // a tx index was invalid. Block 0 folds this call's error into the sticky word.
 __global__ __launch_bounds__(256) void finish_kernel(const double* __restrict__ partials,
                                                      const double* __restrict__ t2_partials,
-                                                     int nblocks, int64_t N, int M, int m,
+                                                     int nblocks, int nblocks2, int64_t N, int M, int m,
                                                      double* stats, const CallWords* call,
                                                      int* sticky) {
   __shared__ double sums[4];
   const int s = blockIdx.x;
   const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t off = ((int64_t)s * 4 + q) * nblocks;
   double t = 0.0;
-  for (int b = lane; b < nblocks; b += 64) t += partials[off + b];
-  if (t2_partials)
-    for (int b = lane; b < nblocks; b += 64) t += t2_partials[off + b];
+  const double* p = partials + ((int64_t)s * 4 + q) * nblocks;
+  for (int b = lane; b < nblocks; b += 64) t += p[b];
+  if (t2_partials) {
+    const double* p2 = t2_partials + ((int64_t)s * 4 + q) * nblocks2;
+    for (int b = lane; b < nblocks2; b += 64) t += p2[b];
+  }
   t = wave_sum(t);
   if (lane == 0) sums[q] = t;
   __syncthreads();
@@ -161,7 +164,7 @@ double from_bf16_bits(uint16_t b) {
 }
 
 // Point side of the matrix-core K slots for one point x (length D), in the
-// order [x_hi | x_lo | x_hi | q_hi, q_lo, q_hi | 0...], q = |x|^2, as
+// order [x_hi | x_lo | x_hi | q_hi, q_lo, q_hi | 1 | 0...], q = |x|^2, as
 // operand bits; hi = round(v), lo = round(v - hi).
 void point_record(const double* x, int D, bool bf, uint16_t* out) {
   const int kp = 16 * mfma_nk(D);
@@ -182,6 +185,7 @@ void point_record(const double* x, int D, bool bf, uint16_t* out) {
   out[3 * D] = qh;
   out[3 * D + 1] = ql;
   out[3 * D + 2] = qh;
+  out[3 * D + 3] = cv(1.0);   // multiplies the sample side's per-sample shift
 }
 
 // Per-SNR scalars of one launch.
@@ -195,21 +199,31 @@ void fill_snr(SnrTable& t, const air_const* c, const double* snr_db, int S) {
 
 // Second-tier workspace: `slots` list entries and `counts` per-wave counters;
 // grows on demand and is kept, so repeated calls of one size allocate nothing.
+void free_t2(air_ctx* ctx) {
+  (void)hipFree(ctx->t2_list);
+  (void)hipFree(ctx->t2_count);
+  (void)hipFree(ctx->t2_comp);
+  (void)hipFree(ctx->t2_comp_s);
+  (void)hipFree(ctx->t2_loc);
+  ctx->t2_list = nullptr;
+  ctx->t2_count = nullptr;
+  ctx->t2_comp = nullptr;
+  ctx->t2_comp_s = nullptr;
+  ctx->t2_loc = nullptr;
+  ctx->t2_slots = ctx->t2_counts = 0;
+}
+
 air_status ensure_t2(air_ctx* ctx, int64_t slots, int64_t counts) {
   if (slots <= ctx->t2_slots && counts <= ctx->t2_counts) return AIR_OK;
   (void)hipStreamSynchronize(ctx->stream);
-  (void)hipFree(ctx->t2_list);
-  (void)hipFree(ctx->t2_count);
-  ctx->t2_list = nullptr;
-  ctx->t2_count = nullptr;
-  ctx->t2_slots = ctx->t2_counts = 0;
+  free_t2(ctx);
   hipError_t e = hipMalloc(&ctx->t2_list, sizeof(unsigned long long) * slots);
   if (e == hipSuccess) e = hipMalloc(&ctx->t2_count, sizeof(unsigned int) * counts);
+  if (e == hipSuccess) e = hipMalloc(&ctx->t2_comp, sizeof(unsigned long long) * slots);
+  if (e == hipSuccess) e = hipMalloc(&ctx->t2_comp_s, slots);
+  if (e == hipSuccess) e = hipMalloc(&ctx->t2_loc, sizeof(unsigned int) * counts);
   if (e != hipSuccess) {
-    (void)hipFree(ctx->t2_list);
-    (void)hipFree(ctx->t2_count);
-    ctx->t2_list = nullptr;
-    ctx->t2_count = nullptr;
+    free_t2(ctx);
     return hip_fail(ctx, e, "second-tier workspace");
   }
   ctx->t2_slots = slots;
@@ -266,7 +280,8 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
     // per (SNR point, wave) a run of list slots, one per sample tile the wave owns
     const int64_t ntiles = (N + 31) / 32;
     const int64_t waves = (int64_t)grid * 4;
-    const int64_t tpw = (ntiles + waves - 1) / waves;
+    const int64_t npairs = (ntiles + 1) / 2;
+    const int64_t tpw = 2 * ((npairs + waves - 1) / waves);
     if (ntiles >= ((int64_t)1 << 32)) return fail(ctx, AIR_E_UNSUPPORTED, "N too large for one call");
     const int64_t sl = S < kMaxSnrPerLaunch ? S : kMaxSnrPerLaunch;
     const air_status st = ensure_t2(ctx, sl * waves * tpw, sl * waves);
@@ -275,6 +290,10 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
     a.t2_count = ctx->t2_count;
     a.t2_partials = ctx->t2_partials;
     a.t2_tpw = (int)tpw;
+    a.t2_comp = ctx->t2_comp;
+    a.t2_comp_s = ctx->t2_comp_s;
+    a.t2_loc = ctx->t2_loc;
+    a.t2_tot = ctx->t2_tot;
   }
   hipError_t e = hipMemsetAsync(ctx->call, 0, sizeof(CallWords), ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "clear call words");
@@ -305,7 +324,7 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
       if (e != hipSuccess) return hip_fail(ctx, e, "timing event record");
     }
     hipLaunchKernelGGL(finish_kernel, dim3(ns), dim3(256), 0, ctx->stream, ctx->partials,
-                       mfma ? ctx->t2_partials : nullptr, grid, N, c->M, c->m,
+                       mfma ? ctx->t2_partials : nullptr, grid, t2_grid(grid), N, c->M, c->m,
                        stats ? stats + 4 * s0 : nullptr, ctx->call, ctx->sticky);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "reduction kernel launch");
@@ -331,6 +350,7 @@ air_status air_create(air_ctx** out, int device, void* hip_stream) {
     ctx->stream = (hipStream_t)hip_stream;
     hipError_t e = hipMalloc(&ctx->partials, sizeof(double) * kMaxGrid * kMaxSnrPerLaunch * 4);
     if (e == hipSuccess) e = hipMalloc(&ctx->t2_partials, sizeof(double) * kMaxGrid * kMaxSnrPerLaunch * 4);
+    if (e == hipSuccess) e = hipMalloc(&ctx->t2_tot, sizeof(unsigned int) * kMaxSnrPerLaunch);
     if (e == hipSuccess) e = hipMalloc(&ctx->call, sizeof(CallWords));
     if (e == hipSuccess) e = hipMalloc(&ctx->sticky, sizeof(int));
     if (e == hipSuccess) e = hipMemset(ctx->call, 0, sizeof(CallWords));
@@ -354,9 +374,9 @@ void air_destroy(air_ctx* ctx) {
   (void)hipFree(ctx->partials);
   (void)hipFree(ctx->call);
   (void)hipFree(ctx->sticky);
-  (void)hipFree(ctx->t2_list);
-  (void)hipFree(ctx->t2_count);
+  free_t2(ctx);
   (void)hipFree(ctx->t2_partials);
+  (void)hipFree(ctx->t2_tot);
   for (hipEvent_t ev : ctx->ev) (void)hipEventDestroy(ev);
   delete ctx;
 }

@@ -51,6 +51,11 @@ struct DemapArgs {
   unsigned int* t2_count;           // [S][waves]: tiles listed by each wave of the launch
   double* t2_partials;              // [S][4][gridDim.x], as partials, from the second tier
   int t2_tpw;                       // list slots per (SNR point, wave)
+  // the lists gathered into one launch-wide list, for a balanced second tier
+  unsigned long long* t2_comp;      // entries in (SNR point, wave, slot) order
+  unsigned char* t2_comp_s;         // SNR point of each gathered entry
+  unsigned int* t2_loc;             // [S][waves]: offset of each wave's list within its SNR point
+  unsigned int* t2_tot;             // [S]: entries listed at each SNR point
   SnrTable snr;
 };
 
@@ -145,6 +150,7 @@ __device__ __noinline__ int slow_nearest(const T* __restrict__ in, int sweep, co
   reload_point<T, D>(in, sweep, xl, sigma, n, tl, y);
   int best = 0;
   T bd = sqdist<T, D>(y, xl);
+#pragma unroll 4
   for (int j = 1; j < M; ++j) {
     T d2 = sqdist<T, D>(y, xl + (int64_t)j * D);
     if (d2 < bd) { bd = d2; best = j; }
@@ -161,17 +167,21 @@ __device__ __noinline__ T slow_rel(const T* __restrict__ in, int sweep, const T*
   reload_point<T, D>(in, sweep, xl, sigma, n, tl, y);
   const T* xr = xl + (int64_t)r * D;
   if (k == -2) return rel_metric<T, D>(y, xr, xl + (int64_t)tl * D, c);
+  // the selection's labels: all of them, or those with bit k equal to b
+  // (index i with b inserted at bit k)
+  const int cnt = k >= 0 ? M >> 1 : M;
+  const int lowmask = k >= 0 ? (1 << k) - 1 : 0;
+  auto label = [&](int i) { return k >= 0 ? (((i & ~lowmask) << 1) | (b << k) | (i & lowmask)) : i; };
   T dmax = -__builtin_huge_val();
-  for (int j = 0; j < M; ++j) {
-    if (k >= 0 && (((j >> k) & 1) != b)) continue;
-    T dj = rel_metric<T, D>(y, xr, xl + (int64_t)j * D, c);
+#pragma unroll 4
+  for (int i = 0; i < cnt; ++i) {
+    T dj = rel_metric<T, D>(y, xr, xl + (int64_t)label(i) * D, c);
     dmax = dj > dmax ? dj : dmax;
   }
   T sum = 0;
-  for (int j = 0; j < M; ++j) {
-    if (k >= 0 && (((j >> k) & 1) != b)) continue;
-    sum += Real<T>::exp2(rel_metric<T, D>(y, xr, xl + (int64_t)j * D, c) - dmax);
-  }
+#pragma unroll 4
+  for (int i = 0; i < cnt; ++i)
+    sum += Real<T>::exp2(rel_metric<T, D>(y, xr, xl + (int64_t)label(i) * D, c) - dmax);
   return dmax + Real<T>::log2(sum);
 }
 
@@ -197,9 +207,10 @@ __device__ __forceinline__ ExactArgs<T> exact_args(const DemapArgs& a, int s) {
 //  total:   sum_j 2^arg_j;  side[2k+b]: the same over bit side (k, b).
 //  arg_t:   arg of the transmitted point (used when tl >= 0).
 // Writes the m LLRs (if llr_out) and returns u, v through the references.
-// Entries below the starvation bound are recomputed exactly.
+// Entries below the starvation bound are recomputed exactly; the return value
+// says whether that happened (the caller counts such items).
 template <typename T, int D>
-__device__ __forceinline__ void finish_item(const ExactArgs<T>& a, int64_t n, int tl,
+__device__ __forceinline__ bool finish_item(const ExactArgs<T>& a, int64_t n, int tl,
                                             T total, const T (&side)[2 * kMaxBits], T arg_t,
                                             T* llr_out, T& u, T& v) {
   const int m = a.m;
@@ -225,7 +236,6 @@ __device__ __forceinline__ void finish_item(const ExactArgs<T>& a, int64_t n, in
     const T* in = a.in;
     const T* xl = a.xl;
     const T sigma = a.sigma, c = a.c;
-    atomicAdd(a.recomputed, 1ull);
     const int r = slow_nearest<T, D>(in, a.sweep, xl, a.M, sigma, n, tl);
     total_slow = !(total >= thr);
     T base = 0;
@@ -256,6 +266,61 @@ __device__ __forceinline__ void finish_item(const ExactArgs<T>& a, int64_t n, in
     for (int k = 0; k < kMaxBits; ++k)
       if (k < m) acc += lam_tot - (((tl >> k) & 1) ? lam[2 * k + 1] : lam[2 * k]);
     v = acc;
+  }
+  return slow;
+}
+
+// Outputs of one FP32-family item from sums in the FP64 frame 2^(a + K64)
+// (the matrix-core path's second tier). Entries below thr64 are recomputed
+// exactly relative to the nearest point r and put back in the frame by
+// adding K64 + a_r; if the total itself is below thr64 every entry is
+// recomputed and all stay relative to a_r. lt_t is log2 of the transmitted
+// point's own term in the frame (used when tl >= 0 and the total is not
+// recomputed). Only the starved entries cost a pass over the constellation.
+// The caller counts the item (it is one of the second tier's items).
+template <int D>
+__device__ __forceinline__ void finish_item_frame64(const ExactArgs<float>& a, int64_t n, int tl,
+                                                    double total, const double (&side)[2 * kMaxBits],
+                                                    double thr64, int K64, double lt_t,
+                                                    float* llr_out, float& u, float& v) {
+  const int m = a.m;
+  const float* in = a.in;
+  const float* xl = a.xl;
+  const float sigma = a.sigma, c = a.c;
+  const int r = slow_nearest<float, D>(in, a.sweep, xl, a.M, sigma, n, tl);
+  const bool total_slow = !(total >= thr64);
+  double lam[2 * kMaxBits];
+  double lam_tot, base = 0.0, delta_t = 0.0;
+  if (total_slow) {
+    lam_tot = (double)slow_rel<float, D>(in, a.sweep, xl, a.M, sigma, c, n, tl, r, -1, 0);
+    if (tl >= 0) delta_t = (double)slow_rel<float, D>(in, a.sweep, xl, a.M, sigma, c, n, tl, r, -2, 0);
+  } else {
+    float y[D];
+    reload_point<float, D>(in, a.sweep, xl, sigma, n, tl, y);
+    base = (double)K64 - (double)c * (double)sqdist<float, D>(y, xl + (int64_t)r * D);
+    lam_tot = ::log2(total);
+  }
+#pragma unroll
+  for (int i = 0; i < 2 * kMaxBits; ++i) {
+    if (i < 2 * m) {
+      if (total_slow || !(side[i] >= thr64))
+        lam[i] = base + (double)slow_rel<float, D>(in, a.sweep, xl, a.M, sigma, c, n, tl, r, i >> 1, i & 1);
+      else
+        lam[i] = ::log2(side[i]);
+    }
+  }
+  if (llr_out) {
+#pragma unroll
+    for (int k = 0; k < kMaxBits; ++k)
+      if (k < m) llr_out[k] = (float)(0.6931471805599453094 * (lam[2 * k] - lam[2 * k + 1]));
+  }
+  if (tl >= 0) {
+    u = (float)(total_slow ? lam_tot - delta_t : lam_tot - lt_t);
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxBits; ++k)
+      if (k < m) acc += lam_tot - (((tl >> k) & 1) ? lam[2 * k + 1] : lam[2 * k]);
+    v = (float)acc;
   }
 }
 

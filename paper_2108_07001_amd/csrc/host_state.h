@@ -34,6 +34,12 @@ struct air_ctx {
   double* t2_partials = nullptr; // kMaxSnrPerLaunch x 4 x kMaxGrid
   int64_t t2_slots = 0;          // capacity of t2_list
   int64_t t2_counts = 0;         // capacity of t2_count
+  // the same entries gathered into one list (capacity t2_slots), the
+  // per-wave offsets (capacity t2_counts) and per-SNR totals
+  unsigned long long* t2_comp = nullptr;
+  unsigned char* t2_comp_s = nullptr;
+  unsigned int* t2_loc = nullptr;
+  unsigned int* t2_tot = nullptr; // kMaxSnrPerLaunch
   // optional timing of the demapping kernels (air_set_timing)
   bool timing = false;
   std::vector<hipEvent_t> ev;    // start/stop pairs recorded since the last read

@@ -1,11 +1,11 @@
 // mfma_inst_bf16_1.hip -- instances of the matrix-core demapping kernels
 // (bfloat16 splits, D = 5..8); split across files so that hipcc runs in parallel.
-#include "mfma_kernels.h"
+#include "mfma_wide.h"
 
 namespace air {
 #define AIR_MFMA_INST(D) \
   hipError_t launch_mfma_bf16_d##D(const DemapArgs& a, const void* rec, int g, hipStream_t s) { \
-    return launch_mfma_td<D, true>(a, rec, g, s); \
+    return launch_mfma_wide_td<D, true>(a, rec, g, s); \
   }
 AIR_MFMA_INST(5)
 AIR_MFMA_INST(6)

@@ -49,8 +49,9 @@ typedef float float16_t __attribute__((ext_vector_type(16)));
 
 constexpr int kTileLevels = kMaxBits - 5;   // label bits carried by the point-tile index
 
-// K slots used by a constellation of dimension D, padded to whole products.
-__host__ __device__ constexpr int mfma_nk(int D) { return (3 * D + 3 + 15) / 16; }
+// K slots used by a constellation of dimension D (3 D + 3 feature slots and
+// one slot for a per-sample shift), padded to whole products.
+__host__ __device__ constexpr int mfma_nk(int D) { return (3 * D + 4 + 15) / 16; }
 
 template <bool BF> struct MfmaOp;
 template <> struct MfmaOp<false> {
@@ -519,37 +520,94 @@ __device__ __forceinline__ void tier2_tile(const SampleTile<D, BF>& smp, const T
     }
     v = (float)pair_sum(vpart);
     u = (float)(lt - ::log2(val64(arg_t)));
-    if (h == 0) atomicAdd(ex.recomputed, 1ull);
   }
-  // beyond the FP64 window, or a sample side outside the f16 range: exact path
+  // beyond the FP64 window: the starved entries take the exact path; a
+  // sample side outside the f16 range leaves no usable entry, so all do
   if (flagged && st2 && h == 0) {
-    float zside[2 * kMaxBits];
+    if (smp.ovf) {
+      total = 0.0;
 #pragma unroll
-    for (int i = 0; i < 2 * kMaxBits; ++i) zside[i] = 0.f;
-    finish_item<float, D>(ex, smp.n, smp.tl, 0.f, zside, arg_t, lout, u, v);
+      for (int i = 0; i < 2 * kMaxBits; ++i) side[i] = 0.0;
+    }
+    finish_item_frame64<D>(ex, smp.n, smp.tl, total, side, thr64, K64, ::log2(val64(arg_t)), lout, u, v);
   }
 }
 
+// Offsets of the per-wave tier-2 lists of SNR point s (block s): an exclusive
+// scan over the first tier's waves in wave order, and the point's total.
+static __global__ __launch_bounds__(256) void t2_scan(const unsigned int* __restrict__ counts, int W,
+                                               unsigned int* __restrict__ loc,
+                                               unsigned int* __restrict__ tot) {
+  __shared__ unsigned int part[256];
+  const int s = blockIdx.x;
+  const unsigned int* c = counts + (int64_t)s * W;
+  const int per = (W + 255) / 256;
+  const int w0 = threadIdx.x * per;
+  const int w1 = w0 + per < W ? w0 + per : W;
+  unsigned int sum = 0;
+  for (int w = w0; w < w1; ++w) sum += c[w];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const unsigned int v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  unsigned int run = part[threadIdx.x] - sum;
+  for (int w = w0; w < w1; ++w) {
+    loc[(int64_t)s * W + w] = run;
+    run += c[w];
+  }
+  if (threadIdx.x == 255) tot[s] = part[255];
+}
+
+// Every listed entry copied to its place in the launch-wide list, in (SNR
+// point, wave, slot) order; one thread per (SNR point, wave).
+static __global__ __launch_bounds__(256) void t2_gather(const unsigned long long* __restrict__ list,
+                                                 const unsigned int* __restrict__ counts,
+                                                 const unsigned int* __restrict__ loc,
+                                                 const unsigned int* __restrict__ tot, int W, int S,
+                                                 int tpw, unsigned long long* __restrict__ comp,
+                                                 unsigned char* __restrict__ comp_s) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)S * W) return;
+  const unsigned int c = counts[i];
+  if (c == 0) return;
+  const int s = (int)(i / W);
+  unsigned int base = 0;
+  for (int k = 0; k < s; ++k) base += tot[k];
+  const int64_t o = (int64_t)base + loc[i];
+  const unsigned long long* src = list + i * tpw;
+  for (unsigned int q = 0; q < c; ++q) {
+    comp[o + q] = src[q];
+    comp_s[o + q] = (unsigned char)s;
+  }
+}
+
+// Second tier: every listed (SNR, sample tile) is re-formed in the FP64 frame.
+// The gathered list is dealt out to the waves round-robin, so the work is
+// spread evenly whatever waves of the first tier listed it; each wave sums
+// its entries per SNR point, and the block reduces its waves in a fixed order.
 template <int D, bool BF, bool HALF, bool TBL>
-__global__ __launch_bounds__(256) void demap_mfma(const DemapArgs a,
-                                                  const typename MfmaOp<BF>::vec* __restrict__ rec,
-                                                  const float* __restrict__ xl) {
+__global__ __launch_bounds__(256) void demap_mfma_t2(const DemapArgs a,
+                                                     const typename MfmaOp<BF>::vec* __restrict__ rec,
+                                                     const float* __restrict__ xl) {
   typedef typename MfmaOp<BF>::vec V;
   typedef SampleTile<D, BF> ST;
   constexpr int NK = ST::NK;
   extern __shared__ double acc_lds[];      // [waves][S][4], then the tables (TBL)
   const int lane = threadIdx.x & 63;
-  const int h = lane >> 5;                 // lane half: label bit 2 of the rows held
-  const int j = lane & 31;                 // sample column within the tile
+  const int h = lane >> 5;
+  const int j = lane & 31;
   const int wave = threadIdx.x >> 6;
   const int waves = blockDim.x >> 6;
   const int S = a.S;
   Tables<BF> tb{a.lab, xl, rec};
   if (TBL) {
-    // small constellations: labels, coordinates and point records in LDS
+    // small constellations in LDS: the tiles' operands and the exact path's
+    // point loops then read no global memory
     const int M = a.M;
-    // byte offsets from the LDS base (integer arithmetic on the offsets, not
-    // on the pointers, so that the accesses stay recognisably LDS accesses)
     char* lds = reinterpret_cast<char*>(acc_lds);
     const int o_lab = waves * S * 4 * (int)sizeof(double);
     const int o_xl = o_lab + M * 4;
@@ -566,152 +624,83 @@ __global__ __launch_bounds__(256) void demap_mfma(const DemapArgs a,
   const int m = a.m;
   const int NT = HALF ? 1 : (a.M >> 5);
   const int ntb = HALF ? 0 : m - 5;
-  const float thr = Real<float>::starve(m);
   float* __restrict__ llr = static_cast<float*>(a.llr);
-  const int64_t ntiles = (a.N + 31) >> 5;
   const int64_t wstride = (int64_t)gridDim.x * waves;
   const int64_t wgid = (int64_t)blockIdx.x * waves + wave;
 
-  // The SNR loop is outermost: each lane keeps its FP64 sums for one SNR point
-  // over all of its wave's sample tiles, and the wave reduces them once.
-  for (int s = 0; s < S; ++s) {
-    double au = 0.0, av = 0.0, auu = 0.0, avv = 0.0;
-    unsigned long long* slots = a.t2_list + ((int64_t)s * wstride + wgid) * a.t2_tpw;
-    int nlisted = 0;
+  // total of the gathered list (lane s holds SNR point s's count)
+  const unsigned int tot_l = lane < S ? a.t2_tot[lane] : 0u;
+  uint64_t E = 0;
+  for (int s = 0; s < S; ++s) E += __builtin_amdgcn_readlane(tot_l, s);
+  // wave w takes entries w, w + waves, ...: every wave gets a share of every
+  // SNR point (the high ones cost far more per entry), in increasing order
+  const int64_t nmine = (int64_t)E > wgid ? ((int64_t)E - wgid + wstride - 1) / wstride : 0;
+  double* wacc = acc_lds + (int64_t)wave * S * 4;
+  for (int i = lane; i < S * 4; i += 64) wacc[i] = 0.0;
+  int s_cur = -1;
+  double au = 0.0, av = 0.0, auu = 0.0, avv = 0.0;
+  auto flush = [&]() {
+    const double w0 = wave_sum(au), w1 = wave_sum(av);
+    const double w2 = wave_sum(auu), w3 = wave_sum(avv);
+    if (lane == 0) {
+      wacc[s_cur * 4 + 0] = w0;
+      wacc[s_cur * 4 + 1] = w1;
+      wacc[s_cur * 4 + 2] = w2;
+      wacc[s_cur * 4 + 3] = w3;
+    }
+    au = av = auu = avv = 0.0;
+  };
+  unsigned long long ents = 0;          // entries b .. b + 63, lane i holding b + i
+  unsigned int ss = 0;                  // and their SNR points
+  unsigned long long items = 0;         // flagged samples this wave finishes
+  for (int64_t r = 0; r < nmine; ++r) {
+    const int k = (int)(r & 63);
+    if (k == 0) {
+      const bool in = r + lane < nmine;
+      const int64_t e = wgid + (r + lane) * wstride;
+      ents = in ? a.t2_comp[e] : 0ull;
+      ss = in ? (unsigned int)a.t2_comp_s[e] : 0u;
+    }
+    const unsigned long long ent =
+        ((unsigned long long)__builtin_amdgcn_readlane((unsigned)(ents >> 32), k) << 32) |
+        (unsigned long long)__builtin_amdgcn_readlane((unsigned)ents, k);
+    const int s = (int)__builtin_amdgcn_readlane(ss, k);
+    if (s != s_cur) {
+      if (s_cur >= 0) flush();
+      s_cur = s;
+    }
+    const int64_t st = (int64_t)(ent & 0xffffffffull);
+    const uint32_t mask = (uint32_t)(ent >> 32);
+    items += (unsigned long long)__builtin_popcount(mask);
     const SampleParams sp = sample_params(a, s);
-    TileInput<D> cur, nxt;
-    if (wgid < ntiles) cur.fetch(sp, wgid, j);
-    for (int64_t st = wgid; st < ntiles; st += wstride) {
-      // next tile's inputs, ahead of use (the last round re-reads the last tile)
-      nxt.fetch(sp, st + wstride < ntiles ? st + wstride : ntiles - 1, j);
-      cur.resolve(sp, tb);
-      ST smp;
-      smp.setup(sp, st, j, h, s == 0, cur);
-      cur = nxt;
+    TileInput<D> ti;
+    ti.load(sp, tb, st, j);
+    ST smp;
+    smp.setup(sp, st, j, h, false, ti);
 
-      float* lout = (llr && smp.valid) ? llr + (int64_t)s * a.llr_stride_s + smp.n * m : nullptr;
-      float u, v;
-      bool need2;
-      tier1_tile<D, BF, HALF>(smp, tb, a.tx != nullptr, j, h, m, NT, ntb, thr, lout, u, v, need2);
-      // items with a starved entry are finished by the second tier; their
-      // tile is listed once for this SNR point with the mask of such lanes
-      const unsigned long long fm = __ballot(need2 && h == 0) & 0xffffffffull;
-      if (fm != 0) {
-        if (lane == 0) slots[nlisted] = (fm << 32) | (unsigned long long)st;
-        ++nlisted;
-      }
-      if (h == 0 && smp.live && smp.tl >= 0 && !need2) {
-        const double du = (double)u, dv = (double)v;
-        au += du;
-        av += dv;
-        auu = __builtin_fma(du, du, auu);
-        avv = __builtin_fma(dv, dv, avv);
-      }
-    }
-    if (lane == 0) a.t2_count[(int64_t)s * wstride + wgid] = (unsigned int)nlisted;
-    const double w0 = wave_sum(au), w1 = wave_sum(av);
-    const double w2 = wave_sum(auu), w3 = wave_sum(avv);
-    if (lane == 0) {
-      double* acc = acc_lds + ((int64_t)wave * S + s) * 4;
-      acc[0] = w0;
-      acc[1] = w1;
-      acc[2] = w2;
-      acc[3] = w3;
+    const bool flagged = (mask >> j) & 1u;
+    float* lout = (llr && smp.valid) ? llr + (int64_t)s * a.llr_stride_s + smp.n * m : nullptr;
+    float u, v;
+    ExactArgs<float> ex = exact_args<float>(a, s);
+    ex.xl = tb.xl;
+    tier2_tile<D, BF, HALF>(smp, tb, ex, a.tx != nullptr, flagged, j, h, m, NT, ntb, lout, u, v);
+    if (flagged && h == 0 && smp.tl >= 0) {
+      const double du = (double)u, dv = (double)v;
+      au += du;
+      av += dv;
+      auu = __builtin_fma(du, du, auu);
+      avv = __builtin_fma(dv, dv, avv);
     }
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < S * 4; i += blockDim.x) {
-    double t = 0.0;
-    for (int w = 0; w < waves; ++w) t += acc_lds[w * S * 4 + i];
-    a.partials[(int64_t)i * gridDim.x + blockIdx.x] = t;
-  }
-}
-
-// Second tier: every listed (SNR, sample tile) is re-formed in the FP64 frame.
-template <int D, bool BF, bool HALF>
-__global__ __launch_bounds__(256) void demap_mfma_t2(const DemapArgs a,
-                                                     const typename MfmaOp<BF>::vec* __restrict__ rec,
-                                                     const float* __restrict__ xl) {
-  typedef SampleTile<D, BF> ST;
-  extern __shared__ double acc_lds[];      // [waves][S][4]
-  const int lane = threadIdx.x & 63;
-  const int h = lane >> 5;
-  const int j = lane & 31;
-  const int wave = threadIdx.x >> 6;
-  const int waves = blockDim.x >> 6;
-  const int S = a.S;
-  const int m = a.m;
-  const int NT = HALF ? 1 : (a.M >> 5);
-  const int ntb = HALF ? 0 : m - 5;
-  float* __restrict__ llr = static_cast<float*>(a.llr);
-  const int64_t wstride = (int64_t)gridDim.x * waves;
-  const int64_t wgid = (int64_t)blockIdx.x * waves + wave;
-  const Tables<BF> tb{a.lab, xl, rec};
-
-  for (int s = 0; s < S; ++s) {
-    double au = 0.0, av = 0.0, auu = 0.0, avv = 0.0;
-    const unsigned long long* slots = a.t2_list + ((int64_t)s * wstride + wgid) * a.t2_tpw;
-    const int nlisted = (int)a.t2_count[(int64_t)s * wstride + wgid];
-    for (int q = 0; q < nlisted; ++q) {
-      const unsigned long long ent = slots[q];
-      const int64_t st = (int64_t)(ent & 0xffffffffull);
-      const uint32_t mask = (uint32_t)(ent >> 32);
-      const SampleParams sp = sample_params(a, s);
-      TileInput<D> ti;
-      ti.load(sp, tb, st, j);
-      ST smp;
-      smp.setup(sp, st, j, h, false, ti);
-
-      const bool flagged = (mask >> j) & 1u;
-      float* lout = (llr && smp.valid) ? llr + (int64_t)s * a.llr_stride_s + smp.n * m : nullptr;
-      float u, v;
-      tier2_tile<D, BF, HALF>(smp, tb, exact_args<float>(a, s), a.tx != nullptr, flagged, j, h, m,
-                              NT, ntb, lout, u, v);
-      if (flagged && h == 0 && smp.tl >= 0) {
-        const double du = (double)u, dv = (double)v;
-        au += du;
-        av += dv;
-        auu = __builtin_fma(du, du, auu);
-        avv = __builtin_fma(dv, dv, avv);
-      }
-    }
-    const double w0 = wave_sum(au), w1 = wave_sum(av);
-    const double w2 = wave_sum(auu), w3 = wave_sum(avv);
-    if (lane == 0) {
-      double* acc = acc_lds + ((int64_t)wave * S + s) * 4;
-      acc[0] = w0;
-      acc[1] = w1;
-      acc[2] = w2;
-      acc[3] = w3;
-    }
-  }
+  if (s_cur >= 0) flush();
+  // one count per wave: same-address atomics from every item would serialise
+  if (lane == 0 && items) atomicAdd(a.recomputed, items);
   __syncthreads();
   for (int i = threadIdx.x; i < S * 4; i += blockDim.x) {
     double t = 0.0;
     for (int w = 0; w < waves; ++w) t += acc_lds[w * S * 4 + i];
     a.t2_partials[(int64_t)i * gridDim.x + blockIdx.x] = t;
   }
-}
-
-template <int D, bool BF>
-hipError_t launch_mfma_td(const DemapArgs& a, const void* rec, int grid, hipStream_t st) {
-  const size_t acc = sizeof(double) * 4 * a.S * 4;
-  const int64_t tbytes = table_bytes(a.M, D);
-  const bool tbl = tbytes <= 40 * 1024;
-  typedef typename MfmaOp<BF>::vec V;
-  const V* r = static_cast<const V*>(rec);
-  const float* x = static_cast<const float*>(a.xl);
-  if (a.M == 16) {
-    hipLaunchKernelGGL((demap_mfma<D, BF, true, true>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
-    hipLaunchKernelGGL((demap_mfma_t2<D, BF, true>), dim3(grid), dim3(256), acc, st, a, r, x);
-  } else {
-    if (tbl)
-      hipLaunchKernelGGL((demap_mfma<D, BF, false, true>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
-    else
-      hipLaunchKernelGGL((demap_mfma<D, BF, false, false>), dim3(grid), dim3(256), acc, st, a, r, x);
-    hipLaunchKernelGGL((demap_mfma_t2<D, BF, false>), dim3(grid), dim3(256), acc, st, a, r, x);
-  }
-  return hipGetLastError();
 }
 
 }  // namespace air

@@ -1,0 +1,512 @@
+// mfma_wide.h -- first tier of the matrix-core path with one sample per lane
+// in the per-sample work.
+//
+// A wave takes 64 samples per round: two 32-sample column groups A (sample
+// tile 2q) and B (tile 2q + 1) that share every point-side operand. Through
+// the point loop each lane keeps the partial sums of its half of the rows,
+// for both groups, exactly as the 32-sample form does. After the loop one
+// v_permlane32_swap per accumulator moves the partial sums so that lane l
+// holds both row halves of sample 64 q + l: lanes 0..31 keep group A's low
+// rows and receive its high rows, lanes 32..63 receive group B's low rows and
+// keep its high rows. Everything per sample -- bit-side folds, starvation
+// checks, the 2m + 1 logarithms, LLR stores, the MI/GMI terms -- then runs
+// once per lane on 64 distinct samples instead of twice on 32.
+//
+// The per-sample shift rides in the spare K slot (every point record holds
+// 1 there): the sample side puts S = K - c|y|^2 rounded down to the operand
+// type, so no accumulator input has to be formed per sample, and every term
+// of a sample is in the same frame 2^(a_j + S + c|y|^2) with
+// S + c|y|^2 <= K: no overflow, and the frame cancels in every output.
+#pragma once
+#include "mfma_kernels.h"
+
+namespace air {
+
+// Running sums of one lane over the point tiles, with LV tile levels.
+template <int NE, int LV>
+struct WideSums {
+  float R[NE];
+  float g0[LV > 0 ? LV : 1], g1[LV > 0 ? LV : 1], gn[LV > 0 ? LV : 1];
+  float tot;
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int l = 0; l < LV; ++l) { g0[l] = 0.f; g1[l] = 0.f; gn[l] = 0.f; }
+    tot = 0.f;
+  }
+  __device__ __forceinline__ void add(float (&ev)[NE], int t, int ntb) {
+    if (t == 0) {
+#pragma unroll
+      for (int e = 0; e < NE; ++e) R[e] = ev[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < NE; ++e) R[e] += ev[e];
+    }
+#pragma unroll
+    for (int w2 = NE / 2; w2 >= 1; w2 >>= 1)
+#pragma unroll
+      for (int e = 0; e < w2; ++e) ev[e] = ev[2 * e] + ev[2 * e + 1];
+    float carry = ev[0];
+    bool placed = false;
+#pragma unroll
+    for (int l = 0; l < LV; ++l) {
+      if (!placed && l < ntb) {
+        if ((t >> l) & 1) {
+          g0[l] += gn[l];
+          g1[l] += carry;
+          carry = gn[l] + carry;
+        } else {
+          gn[l] = carry;
+          placed = true;
+        }
+      }
+    }
+    if (!placed) tot = carry;
+  }
+};
+
+// Exchange of a pair of per-group values between the lane halves: returns
+// (low-row half, high-row half) of the lane's own sample.
+__device__ __forceinline__ void own_halves(float a, float b, float& lo, float& hi) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  lo = __uint_as_float(r[0]);
+  hi = __uint_as_float(r[1]);
+}
+
+// Sample side of one 32-sample group for this lane's K half: features of the
+// sample in column j, with the shift S in the spare K slot.
+template <int D, bool BF>
+struct WideOperand {
+  typedef typename MfmaOp<BF>::vec V;
+  typedef typename MfmaOp<BF>::elem E;
+  static constexpr int NK = mfma_nk(D);
+  static constexpr int KP = 16 * NK;
+  V B[NK];
+  bool ovf;      // a sample-side value outside the operand range: exact path
+
+  __device__ __forceinline__ void build(const float (&y)[D], float c, int m, int h) {
+    const float K = Real<float>::shift(m);
+    float yy = 0.0f;
+#pragma unroll
+    for (int d = 0; d < D; ++d) yy = __builtin_fmaf(y[d], y[d], yy);
+    E F[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) F[k] = (E)0.0f;
+    ovf = !(c < 60000.0f);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const float w = 2.0f * c * y[d];
+      ovf |= !(__builtin_fabsf(w) < 60000.0f);
+      E hi, lo;
+      split2<BF>(w, hi, lo);
+      F[d] = hi;
+      F[D + d] = hi;
+      F[2 * D + d] = lo;
+    }
+    {
+      E hi, lo;
+      split2<BF>(-c, hi, lo);
+      F[3 * D] = hi;
+      F[3 * D + 1] = hi;
+      F[3 * D + 2] = lo;
+    }
+    // S = K - c|y|^2, rounded to the operand type from below: lowering the
+    // argument by more than one unit in the last place before rounding to
+    // nearest keeps the rounded value <= S
+    const float s0 = __builtin_fmaf(-c, yy, K);
+    const float ulp = BF ? 0x1p-7f : 0x1p-10f;
+    F[3 * D + 3] = (E)(s0 - __builtin_fabsf(s0) * ulp);
+    ovf |= !(__builtin_fabsf(s0) < 60000.0f);
+    if (BF) ovf = false;  // bfloat16 has the FP32 range
+    const uint32_t hmask = 0u - (uint32_t)h;
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+      uint32_t wd[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint32_t w0, w1;
+        E p0[2] = {F[16 * kk + 2 * q], F[16 * kk + 2 * q + 1]};
+        E p1[2] = {F[16 * kk + 8 + 2 * q], F[16 * kk + 8 + 2 * q + 1]};
+        __builtin_memcpy(&w0, p0, 4);
+        __builtin_memcpy(&w1, p1, 4);
+        wd[q] = (w0 & ~hmask) | (w1 & hmask);
+      }
+      __builtin_memcpy(&B[kk], wd, 16);
+    }
+  }
+
+  __device__ __forceinline__ float16_t product(const V (&A)[NK]) const {
+    const float16_t zero = {};
+    float16_t acc = MfmaOp<BF>::mma(A[0], B[0], zero);
+#pragma unroll
+    for (int kk = 1; kk < NK; ++kk) acc = MfmaOp<BF>::mma(A[kk], B[kk], acc);
+    return acc;
+  }
+};
+
+// Element (j & 3) | ((j >> 3) << 2) of a product tile: the diagonal entry of
+// column j in the lane half (j >> 2) & 1 (a tree of bitwise selects).
+__device__ __forceinline__ float diag_pick(const float16_t& acc, int j) {
+  auto pick = [](float a, float b, uint32_t mask) {
+    return __builtin_bit_cast(float, (__builtin_bit_cast(uint32_t, a) & ~mask) |
+                                         (__builtin_bit_cast(uint32_t, b) & mask));
+  };
+  const uint32_t m0 = 0u - (uint32_t)(j & 1), m1 = 0u - (uint32_t)((j >> 1) & 1);
+  const uint32_t m2 = 0u - (uint32_t)((j >> 3) & 1), m3 = 0u - (uint32_t)((j >> 4) & 1);
+  float v8[8], v4[4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v8[i] = pick(acc[2 * i], acc[2 * i + 1], m0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v4[i] = pick(v8[2 * i], v8[2 * i + 1], m1);
+  return pick(pick(v4[0], v4[1], m2), pick(v4[2], v4[3], m2), m3);
+}
+
+// Raw global inputs of one sample, loaded a round ahead of use (see
+// TileInput::fetch for why the loads are unconditional and unmasked).
+template <int D>
+struct RawInput {
+  uint32_t t;
+  float z[D];
+  __device__ __forceinline__ void fetch(const SampleParams& p, int64_t st, int j) {
+    const int64_t n = st * 32 + j;
+    const int64_t nc = n < p.N ? n : p.N - 1;
+    const uint32_t* __restrict__ txp = p.tx ? p.tx : reinterpret_cast<const uint32_t*>(p.in);
+    t = txp[nc];
+    const float* __restrict__ in = p.in + nc * D;
+#pragma unroll
+    for (int d = 0; d < D; ++d) z[d] = in[d];
+  }
+};
+
+// One group's sample for this lane's column j: validity, label and y.
+template <int D>
+struct WideSample {
+  int64_t n;
+  bool valid, live;
+  int tl;          // label of the transmitted point (-1 none, -2 invalid index)
+  int tq;          // an in-bounds label for record reads
+  float y[D];
+  template <bool BF>
+  __device__ __forceinline__ void setup(const SampleParams& p, const Tables<BF>& tb, int64_t st, int j,
+                                        bool flag_errors, const RawInput<D>& ri) {
+    n = st * 32 + j;
+    valid = n < p.N;
+    const bool inb = ri.t < (uint32_t)p.M;
+    const int lab = inb ? (int)tb.lab[ri.t] : 0;
+    tl = -1;
+    if (valid && p.tx) {
+      if (!inb) {
+        if (flag_errors) atomicOr(p.err, 1);
+        tl = -2;
+      } else {
+        tl = lab;
+      }
+    }
+    live = valid && tl != -2;
+    tq = tl >= 0 ? tl : 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const float zi = live ? ri.z[d] : 0.0f;
+      y[d] = (p.sweep && live) ? __builtin_fmaf(p.sigma, zi, tb.xl[lab * D + d]) : zi;
+    }
+  }
+};
+
+// First tier, 64 samples per wave round. The exact-size forms of small D are
+// held to 168 registers (three waves per SIMD); what little the allocator
+// then keeps in scratch is reloaded once per SNR point, outside the sample
+// loop. MB = log2 M for the small sets
+// compiled at their exact size (M = 16, 32, 64: every per-bit loop and the
+// point loop are then static), 0 for any M >= 32 taken at run time. The t2
+// list and partial-sum layouts are those of demap_mfma, so the second-tier
+// kernel is shared.
+template <int D, bool BF, bool TBL, int MB>
+__global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(const DemapArgs a,
+                                                    const typename MfmaOp<BF>::vec* __restrict__ rec,
+                                                    const float* __restrict__ xl) {
+  typedef typename MfmaOp<BF>::vec V;
+  typedef WideOperand<D, BF> OP;
+  constexpr bool HALF = MB == 4;                                   // 16-point tiles
+  constexpr int LV = MB == 0 ? kTileLevels : (MB > 5 ? MB - 5 : 0);  // tile levels carried
+  constexpr int NK = OP::NK;
+  constexpr int NE = HALF ? 8 : 16;
+  constexpr int NEB = HALF ? 3 : 4;       // element bits carrying label bits
+  extern __shared__ double acc_lds[];      // [waves][S][4], then the tables (TBL)
+  const int lane = threadIdx.x & 63;
+  const int h = lane >> 5;
+  const int j = lane & 31;
+  const int wave = threadIdx.x >> 6;
+  const int waves = blockDim.x >> 6;
+  const int S = a.S;
+  Tables<BF> tb{a.lab, xl, rec};
+  if (TBL) {
+    const int M = a.M;
+    char* lds = reinterpret_cast<char*>(acc_lds);
+    const int o_lab = waves * S * 4 * (int)sizeof(double);
+    const int o_xl = o_lab + M * 4;
+    const int o_rec = (o_xl + M * D * 4 + 15) & ~15;
+    uint32_t* l_lab = reinterpret_cast<uint32_t*>(lds + o_lab);
+    float* l_xl = reinterpret_cast<float*>(lds + o_xl);
+    V* l_rec = reinterpret_cast<V*>(lds + o_rec);
+    for (int i = threadIdx.x; i < M; i += blockDim.x) l_lab[i] = a.lab[i];
+    for (int i = threadIdx.x; i < M * D; i += blockDim.x) l_xl[i] = xl[i];
+    for (int i = threadIdx.x; i < M * NK * 2; i += blockDim.x) l_rec[i] = rec[i];
+    __syncthreads();
+    tb = Tables<BF>{l_lab, l_xl, l_rec};
+  }
+  const int m = MB ? MB : a.m;
+  const int NT = MB ? (HALF ? 1 : 1 << (MB - 5)) : (a.M >> 5);
+  const int ntb = MB ? LV : m - 5;
+  const float thr = Real<float>::starve(m);
+  float* __restrict__ llr = static_cast<float*>(a.llr);
+  const int64_t ntiles = (a.N + 31) >> 5;
+  const int64_t npairs = (ntiles + 1) >> 1;
+  const int64_t wstride = (int64_t)gridDim.x * waves;
+  const int64_t wgid = (int64_t)blockIdx.x * waves + wave;
+  const bool hj = (j >> 2) & 1;           // lane half holding row j of a tile
+
+  for (int s = 0; s < S; ++s) {
+    double au = 0.0, av = 0.0, auu = 0.0, avv = 0.0;
+    unsigned long long* slots = a.t2_list + ((int64_t)s * wstride + wgid) * a.t2_tpw;
+    int nlisted = 0;
+    const SampleParams sp = sample_params(a, s);
+    RawInput<D> curA, curB, nxtA, nxtB;
+    if (wgid < npairs) {
+      curA.fetch(sp, 2 * wgid, j);
+      curB.fetch(sp, 2 * wgid + 1, j);
+    }
+    for (int64_t q = wgid; q < npairs; q += wstride) {
+      {
+        const int64_t qn = q + wstride < npairs ? q + wstride : npairs - 1;
+        nxtA.fetch(sp, 2 * qn, j);          // next round's inputs, ahead of use
+        nxtB.fetch(sp, 2 * qn + 1, j);
+      }
+      WideSample<D> smA, smB;
+      smA.setup(sp, tb, 2 * q, j, s == 0 && h == 0, curA);
+      smB.setup(sp, tb, 2 * q + 1, j, s == 0 && h == 0, curB);
+      curA = nxtA;
+      curB = nxtB;
+      OP opA, opB;
+      opA.build(smA.y, sp.c, m, h);
+      opB.build(smB.y, sp.c, m, h);
+
+      // the transmitted points' own terms: diagonals of the products whose A
+      // rows are the groups' transmitted points
+      float arg_t = 0.f;
+      if (a.tx) {
+        V At[NK];
+        const V* ra = tb.rec + ((int64_t)smA.tq * NK) * 2 + h;
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) At[kk] = ra[2 * kk];
+        const float pa = diag_pick(opA.product(At), j);
+        const V* rb = tb.rec + ((int64_t)smB.tq * NK) * 2 + h;
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) At[kk] = rb[2 * kk];
+        const float pb = diag_pick(opB.product(At), j);
+        float lo, hi;
+        own_halves(pa, pb, lo, hi);
+        arg_t = hj ? hi : lo;
+      }
+
+      WideSums<NE, LV> sA, sB;
+      sA.init();
+      sB.init();
+      {
+        V A[NK];
+        const V* rp = rec_row<BF, HALF, NK>(tb.rec, 0, j, h);
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) A[kk] = rp[2 * kk];
+        for (int t = 0; t < NT; ++t) {
+          const float16_t accA = opA.product(A);
+          const float16_t accB = opB.product(A);
+          if (t + 1 < NT) {
+            const V* rq = rec_row<BF, HALF, NK>(tb.rec, t + 1, j, h);
+#pragma unroll
+            for (int kk = 0; kk < NK; ++kk) A[kk] = rq[2 * kk];
+          }
+          float ev[NE];
+#pragma unroll
+          for (int e = 0; e < NE; ++e) ev[e] = Real<float>::exp2(accA[e]);
+          sA.add(ev, t, ntb);
+#pragma unroll
+          for (int e = 0; e < NE; ++e) ev[e] = Real<float>::exp2(accB[e]);
+          sB.add(ev, t, ntb);
+        }
+      }
+      // own sample of this lane: group A in lanes 0..31, group B in 32..63
+      const int64_t n = h ? smB.n : smA.n;
+      const bool valid = h ? smB.valid : smA.valid;
+      const bool live = h ? smB.live : smA.live;
+      const int tl = h ? smB.tl : smA.tl;
+      const bool ovf = h ? opB.ovf : opA.ovf;
+
+      // both row halves of the own sample
+      float r0[NE], r1[NE];
+#pragma unroll
+      for (int e = 0; e < NE; ++e) own_halves(sA.R[e], sB.R[e], r0[e], r1[e]);
+      float side[2 * kMaxBits];
+#pragma unroll
+      for (int i = 0; i < 2 * kMaxBits; ++i) side[i] = 0.f;
+      float total;
+      {
+        float t0, t1;
+        own_halves(sA.tot, sB.tot, t0, t1);
+        total = t0 + t1;
+      }
+#pragma unroll
+      for (int l = 0; l < LV; ++l)
+        if (l < ntb) {
+          float x0, x1;
+          own_halves(sA.g0[l], sB.g0[l], x0, x1);
+          side[2 * (5 + l)] = x0 + x1;
+          own_halves(sA.g1[l], sB.g1[l], x0, x1);
+          side[2 * (5 + l) + 1] = x0 + x1;
+        }
+      {
+        // label bit 2 is the row half
+        float c0 = r0[0], c1 = r1[0];
+#pragma unroll
+        for (int e = 1; e < NE; ++e) {
+          c0 += r0[e];
+          c1 += r1[e];
+        }
+        side[4] = c0;
+        side[5] = c1;
+      }
+      {
+        // label bits 0, 1, 3 (, 4) are the element bits 0, 1, 2 (, 3)
+        float cur[NE];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) cur[e] = r0[e] + r1[e];
+#pragma unroll
+        for (int eb = 0; eb < NEB; ++eb) {
+          const int half = NE >> (eb + 1);
+          float a0 = cur[0], a1 = cur[1];
+#pragma unroll
+          for (int i = 1; i < NE / 2; ++i)
+            if (i < half) {
+              a0 += cur[2 * i];
+              a1 += cur[2 * i + 1];
+            }
+#pragma unroll
+          for (int i = 0; i < NE / 2; ++i)
+            if (i < half) cur[i] = cur[2 * i] + cur[2 * i + 1];
+          const int k = eb < 2 ? eb : eb + 1;
+          side[2 * k] = a0;
+          side[2 * k + 1] = a1;
+        }
+      }
+
+      float* lout = (llr && valid) ? llr + (int64_t)s * a.llr_stride_s + n * m : nullptr;
+      bool starved = ovf || !(total >= thr);
+#pragma unroll
+      for (int i = 0; i < 2 * kMaxBits; ++i)
+        if (i < 2 * m) starved |= !(side[i] >= thr);
+      float u = 0.f, v = 0.f;
+      if (live && !starved) {
+        const float lam_tot = Real<float>::log2(total);
+        float L[kMaxBits];
+#pragma unroll
+        for (int k = 0; k < kMaxBits; ++k) {
+          if (k < m) {
+            const float l0 = Real<float>::log2(side[2 * k]), l1 = Real<float>::log2(side[2 * k + 1]);
+            L[k] = Real<float>::ln2() * (l0 - l1);
+            if (tl >= 0) v += lam_tot - (((tl >> k) & 1) ? l1 : l0);
+          }
+        }
+        if (lout) {
+#pragma unroll
+          for (int k = 0; k < kMaxBits; ++k)
+            if (k < m) lout[k] = L[k];
+        }
+        u = lam_tot - Real<float>::log2(Real<float>::exp2(arg_t));
+      }
+      // items with a starved entry are finished by the second tier: each of
+      // the two sample tiles is listed with the mask of its starved lanes
+      const bool need2 = live && starved;
+      const unsigned long long bm = __ballot(need2);
+      const unsigned long long mlo = bm & 0xffffffffull, mhi = bm >> 32;
+      if (mlo) {
+        if (lane == 0) slots[nlisted] = (mlo << 32) | (unsigned long long)(2 * q);
+        ++nlisted;
+      }
+      if (mhi) {
+        if (lane == 0) slots[nlisted] = (mhi << 32) | (unsigned long long)(2 * q + 1);
+        ++nlisted;
+      }
+      if (valid && !live && lout)
+        for (int k = 0; k < m; ++k) lout[k] = Real<float>::nan();
+      if (live && tl >= 0 && !need2) {
+        const double du = (double)u, dv = (double)v;
+        au += du;
+        av += dv;
+        auu = __builtin_fma(du, du, auu);
+        avv = __builtin_fma(dv, dv, avv);
+      }
+    }
+    if (lane == 0) a.t2_count[(int64_t)s * wstride + wgid] = (unsigned int)nlisted;
+    const double w0 = wave_sum(au), w1 = wave_sum(av);
+    const double w2 = wave_sum(auu), w3 = wave_sum(avv);
+    if (lane == 0) {
+      double* acc = acc_lds + ((int64_t)wave * S + s) * 4;
+      acc[0] = w0;
+      acc[1] = w1;
+      acc[2] = w2;
+      acc[3] = w3;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < S * 4; i += blockDim.x) {
+    double t = 0.0;
+    for (int w = 0; w < waves; ++w) t += acc_lds[w * S * 4 + i];
+    a.partials[(int64_t)i * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// Blocks of a second-tier launch: at most 512 (2048 waves, one round of the
+// chip at two waves per SIMD); the gathered list is spread over them evenly.
+__host__ __device__ inline int t2_grid(int grid) { return grid < 512 ? grid : 512; }
+
+// Offsets and the gathered list of the first tier's tier-2 entries.
+inline void launch_t2_gather(const DemapArgs& a, int grid, hipStream_t st) {
+  const int W = grid * 4;
+  hipLaunchKernelGGL(t2_scan, dim3(a.S), dim3(256), 0, st, a.t2_count, W, a.t2_loc, a.t2_tot);
+  const int64_t n = (int64_t)a.S * W;
+  hipLaunchKernelGGL(t2_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a.t2_list, a.t2_count,
+                     a.t2_loc, a.t2_tot, W, a.S, a.t2_tpw, a.t2_comp, a.t2_comp_s);
+}
+
+// Both tiers for one (D, operand type): the wide first tier in the variant
+// the constellation size calls for, then the shared second tier.
+template <int D, bool BF>
+hipError_t launch_mfma_wide_td(const DemapArgs& a, const void* rec, int grid, hipStream_t st) {
+  const size_t acc = sizeof(double) * 4 * a.S * 4;
+  const int64_t tbytes = table_bytes(a.M, D);
+  const bool tbl = tbytes <= 40 * 1024;
+  typedef typename MfmaOp<BF>::vec V;
+  const V* r = static_cast<const V*>(rec);
+  const float* x = static_cast<const float*>(a.xl);
+  // the exact-size forms hold their tables in LDS (at most 12.5 KB for M = 64)
+  if (a.M == 16) {
+    hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 4>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
+    launch_t2_gather(a, grid, st);
+    hipLaunchKernelGGL((demap_mfma_t2<D, BF, true, true>), dim3(t2_grid(grid)), dim3(256), acc + tbytes, st, a, r, x);
+    return hipGetLastError();
+  }
+  if (a.M == 32)
+    hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 5>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
+  else if (a.M == 64)
+    hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 6>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
+  else if (tbl)
+    hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 0>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
+  else
+    hipLaunchKernelGGL((demap_mfma_w<D, BF, false, 0>), dim3(grid), dim3(256), acc, st, a, r, x);
+  launch_t2_gather(a, grid, st);
+  if (tbl)
+    hipLaunchKernelGGL((demap_mfma_t2<D, BF, false, true>), dim3(t2_grid(grid)), dim3(256), acc + tbytes, st, a,
+                       r, x);
+  else
+    hipLaunchKernelGGL((demap_mfma_t2<D, BF, false, false>), dim3(t2_grid(grid)), dim3(256), acc, st, a, r, x);
+  return hipGetLastError();
+}
+
+}  // namespace air

@@ -149,10 +149,12 @@ __global__ __launch_bounds__(256) void serve_tier2(const JobDesc* __restrict__ j
       const Tables<BF> tb{jd.lab, jd.xl, static_cast<const V*>(jd.rec)};
       const ExactArgs<float> ex{jd.in, jd.sweep, jd.xl, jd.M, m, jd.sigma, jd.c, &jd.out->recomputed};
       const unsigned long long* slots = jd.list + li * jd.chunk;
+      unsigned long long items = 0;
       for (int q = 0; q < nlisted; ++q) {
         const unsigned long long ent = slots[q];
         const int64_t st = (int64_t)(ent & 0xffffffffull);
         const uint32_t mask = (uint32_t)(ent >> 32);
+        items += (unsigned long long)__builtin_popcount(mask);
         TileInput<D> ti;
         ti.load(sp, tb, st, j);
         ST smp;
@@ -169,6 +171,7 @@ __global__ __launch_bounds__(256) void serve_tier2(const JobDesc* __restrict__ j
           avv = __builtin_fma(dv, dv, avv);
         }
       }
+      if (lane == 0) atomicAdd(&jd.out->recomputed, items);
     }
     const double w0 = wave_sum(au), w1 = wave_sum(av);
     const double w2 = wave_sum(auu), w3 = wave_sum(avv);

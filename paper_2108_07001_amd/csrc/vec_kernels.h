@@ -57,6 +57,7 @@ __global__ __launch_bounds__(kBlock) void demap_vec(const DemapArgs a, const T* 
   T* __restrict__ llr = static_cast<T*>(a.llr);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t rounds = (a.N + stride - 1) / stride;
+  unsigned int slow_items = 0;   // items this lane sent through the exact path
 
   for (int64_t r = 0; r < rounds; ++r) {
     const int64_t n = r * stride + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void demap_vec(const DemapArgs a, const T* 
         T arg_t = 0;
         if (tl >= 0) arg_t = Real<T>::fma(-c, sqdist<T, D>(y, xl + (int64_t)tl * D), K);
         T u = 0, v = 0;
-        finish_item<T, D>(exact_args<T>(a, s), n, tl, total, side, arg_t, lout, u, v);
+        slow_items += finish_item<T, D>(exact_args<T>(a, s), n, tl, total, side, arg_t, lout, u, v) ? 1u : 0u;
         if (tl >= 0) {
           su = (double)u;
           sv = (double)v;
@@ -158,6 +159,9 @@ __global__ __launch_bounds__(kBlock) void demap_vec(const DemapArgs a, const T* 
       }
     }
   }
+  // one count per wave: same-address atomics from every item would serialise
+  const double wslow = wave_sum((double)slow_items);
+  if (lane == 0 && wslow > 0.0) atomicAdd(a.recomputed, (unsigned long long)wslow);
   __syncthreads();
   for (int i = threadIdx.x; i < S * 4; i += blockDim.x) {
     double t = 0.0;

@@ -1,5 +1,5 @@
 """GPU tests of the serving loop (air_server_*): parity with the FP64 oracle,
-bitwise agreement with the one-shot entry points, alone-vs-mix identity,
+agreement with the one-shot entry points, bitwise alone-vs-mix identity,
 admission under the footprint budget, latency stamps and error paths."""
 import time
 
@@ -73,9 +73,10 @@ def test_serve_oracle_parity(ctx, consts, prec, M, D):
 
 @pytest.mark.parametrize("M,D", MIX)
 def test_serve_matches_one_shot(ctx, consts, M, D):
-    """Same received block through air_mi_gmi and through the server: the LLRs
-    are bitwise equal (same per-sample arithmetic), the statistics agree to
-    FP64 rounding (the two sum in different fixed orders)."""
+    """Same received block through air_mi_gmi and through the server. The
+    one-shot kernel puts each sample's terms in a frame shifted by a rounded
+    per-sample constant, the serving kernel in the fixed frame: the results
+    agree to FP32 rounding of the terms."""
     X, lab, c = consts[M]
     N = 4099
     tx, z = _block(M, D, N, 11 + M)
@@ -87,10 +88,10 @@ def test_serve_matches_one_shot(ctx, consts, M, D):
     L2 = torch.empty((N, c.m), device=ctx.torch_device)
     r = _run_alone(sv, dict(c=c, inp=to_dev(Y), tx=tx_dev(tx), snr_db=snr, prec="fp16x3", llr=L2))
     sv.close()
-    assert torch.equal(L1, L2)
+    assert_llr(L2.cpu().numpy(), L1.cpu().numpy(), 1e-4)
     st1 = st1.cpu().numpy()
     st2 = np.array([r["mi"], r["gmi"], r["se_mi"], r["se_gmi"]])
-    assert np.allclose(st1, st2, rtol=1e-12, atol=1e-12), (st1, st2)
+    assert np.allclose(st1, st2, rtol=1e-6, atol=1e-7), (st1, st2)
 
 
 def _mix_jobs(ctx, consts, n, seed, host_share=0.5):
@@ -214,7 +215,7 @@ def test_llr_only_job(ctx, consts):
     r = _run_alone(sv, dict(c=c, inp=to_dev(Y), snr_db=12.0, prec="bf16x3", llr=L2))
     sv.close()
     assert r["status"] == air.AIR_OK and np.isnan(_stats(r)).all()
-    assert torch.equal(L1, L2)
+    assert_llr(L2.cpu().numpy(), L1.cpu().numpy(), 1e-4)
 
 
 def test_submit_errors(ctx, consts):
