@@ -146,9 +146,10 @@ air_status air_sweep(air_ctx *ctx, const air_const *c, const uint32_t *tx_dev,
 int64_t air_last_recomputed(air_ctx *ctx);
 
 /* Kernel timing for measurement tools. While enabled, every call records a
- * pair of HIP events on the context's stream around each of its demapping
- * kernel launches (not around the small reduction kernel that follows).
- * Enabling or disabling discards the recorded pairs. */
+ * pair of HIP events on the context's stream around each launch of its main
+ * demapping kernel: the vector kernel, or the first tier of the matrix-core
+ * forms (not around their second tier or the small reduction kernel that
+ * follows). Enabling or disabling discards the recorded pairs. */
 air_status air_set_timing(air_ctx *ctx, int enable);
 
 /* Sum of the demapping-kernel durations recorded since timing was enabled or

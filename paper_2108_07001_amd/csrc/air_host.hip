@@ -41,8 +41,8 @@ static const VecFn kVecF64[kMaxD + 1] = {
 #undef AIR_FN
 
 // Matrix-core launchers, one per (operand type, D), defined in mfma_inst_*.hip.
-using MfmaFn = hipError_t (*)(const DemapArgs&, const void*, int, hipStream_t);
-#define AIR_DECL(tag, D) hipError_t launch_mfma_##tag##_d##D(const DemapArgs&, const void*, int, hipStream_t);
+using MfmaFn = hipError_t (*)(const DemapArgs&, const void*, int, hipStream_t, int);
+#define AIR_DECL(tag, D) hipError_t launch_mfma_##tag##_d##D(const DemapArgs&, const void*, int, hipStream_t, int);
 #define AIR_DECL_ALL(tag)                                                                        \
   AIR_DECL(tag, 1) AIR_DECL(tag, 2) AIR_DECL(tag, 3) AIR_DECL(tag, 4) AIR_DECL(tag, 5)          \
   AIR_DECL(tag, 6) AIR_DECL(tag, 7) AIR_DECL(tag, 8) AIR_DECL(tag, 9) AIR_DECL(tag, 10)         \
@@ -317,11 +317,15 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
       e = hipEventRecord(evp[0], ctx->stream);
       if (e != hipSuccess) return hip_fail(ctx, e, "timing event record");
     }
-    e = mfma ? mfn(a, rec, grid, ctx->stream) : vfn(a, grid, ctx->stream);
+    e = mfma ? mfn(a, rec, grid, ctx->stream, 0) : vfn(a, grid, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "demapping kernel launch");
     if (evp) {
       e = hipEventRecord(evp[1], ctx->stream);
       if (e != hipSuccess) return hip_fail(ctx, e, "timing event record");
+    }
+    if (mfma) {
+      e = mfn(a, rec, grid, ctx->stream, 1);
+      if (e != hipSuccess) return hip_fail(ctx, e, "second-tier launch");
     }
     hipLaunchKernelGGL(finish_kernel, dim3(ns), dim3(256), 0, ctx->stream, ctx->partials,
                        mfma ? ctx->t2_partials : nullptr, grid, t2_grid(grid), N, c->M, c->m,

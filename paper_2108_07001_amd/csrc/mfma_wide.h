@@ -477,35 +477,39 @@ inline void launch_t2_gather(const DemapArgs& a, int grid, hipStream_t st) {
 
 // Both tiers for one (D, operand type): the wide first tier in the variant
 // the constellation size calls for, then the shared second tier.
+// One tier of the matrix-core path for one (D, operand type): part 0 is the
+// wide first tier in the variant the constellation size calls for, part 1 the
+// gather of its lists and the shared second tier.
 template <int D, bool BF>
-hipError_t launch_mfma_wide_td(const DemapArgs& a, const void* rec, int grid, hipStream_t st) {
+hipError_t launch_mfma_wide_td(const DemapArgs& a, const void* rec, int grid, hipStream_t st, int part) {
   const size_t acc = sizeof(double) * 4 * a.S * 4;
   const int64_t tbytes = table_bytes(a.M, D);
   const bool tbl = tbytes <= 40 * 1024;
   typedef typename MfmaOp<BF>::vec V;
   const V* r = static_cast<const V*>(rec);
   const float* x = static_cast<const float*>(a.xl);
-  // the exact-size forms hold their tables in LDS (at most 12.5 KB for M = 64)
-  if (a.M == 16) {
-    hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 4>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
-    launch_t2_gather(a, grid, st);
-    hipLaunchKernelGGL((demap_mfma_t2<D, BF, true, true>), dim3(t2_grid(grid)), dim3(256), acc + tbytes, st, a, r, x);
+  if (part == 0) {
+    // the exact-size forms hold their tables in LDS (at most 12.5 KB for M = 64)
+    if (a.M == 16)
+      hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 4>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
+    else if (a.M == 32)
+      hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 5>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
+    else if (a.M == 64)
+      hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 6>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
+    else if (tbl)
+      hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 0>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
+    else
+      hipLaunchKernelGGL((demap_mfma_w<D, BF, false, 0>), dim3(grid), dim3(256), acc, st, a, r, x);
     return hipGetLastError();
   }
-  if (a.M == 32)
-    hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 5>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
-  else if (a.M == 64)
-    hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 6>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
-  else if (tbl)
-    hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 0>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
-  else
-    hipLaunchKernelGGL((demap_mfma_w<D, BF, false, 0>), dim3(grid), dim3(256), acc, st, a, r, x);
   launch_t2_gather(a, grid, st);
-  if (tbl)
-    hipLaunchKernelGGL((demap_mfma_t2<D, BF, false, true>), dim3(t2_grid(grid)), dim3(256), acc + tbytes, st, a,
-                       r, x);
+  const dim3 g2(t2_grid(grid));
+  if (a.M == 16)
+    hipLaunchKernelGGL((demap_mfma_t2<D, BF, true, true>), g2, dim3(256), acc + tbytes, st, a, r, x);
+  else if (tbl)
+    hipLaunchKernelGGL((demap_mfma_t2<D, BF, false, true>), g2, dim3(256), acc + tbytes, st, a, r, x);
   else
-    hipLaunchKernelGGL((demap_mfma_t2<D, BF, false, false>), dim3(t2_grid(grid)), dim3(256), acc, st, a, r, x);
+    hipLaunchKernelGGL((demap_mfma_t2<D, BF, false, false>), g2, dim3(256), acc, st, a, r, x);
   return hipGetLastError();
 }
 
