@@ -29,15 +29,19 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 
 def source_hash() -> str:
-    """Digest of the HIP sources, to tell whether stored counter data still
-    describes the kernels that are built."""
+    """Digest of the HIP sources' code (comments and blank lines dropped), to
+    tell whether stored counter data still describes the kernels built."""
     import glob
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_2108_07001_amd", "csrc", "*"))):
         if f.endswith((".h", ".hip")):
             h.update(os.path.basename(f).encode())
-            h.update(open(f, "rb").read())
+            for line in open(f).read().splitlines():
+                code = re.sub(r"//.*$", "", line).rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -1,20 +1,25 @@
-// mfma_kernels.h -- matrix-core demapping kernels (AIR_FP16X3, AIR_BF16X3).
+// mfma_kernels.h -- matrix-core demapping (AIR_FP16X3, AIR_BF16X3): the
+// exponent-tile arithmetic, the per-tile bodies of both tiers, the second-tier
+// kernel and its list gathering. The first-tier kernel of the sweep and
+// air_mi_gmi calls is in mfma_wide.h; the serving kernels in serve_kernels.h.
 //
-// The exponent tile arg[i][j] = K - c |y_j - x_i|^2 of 32 constellation points
+// The exponent tile arg[i][j] = a_j(x_i) + shift of 32 constellation points
 // (rows i) by 32 received samples (columns j) is one chain of
 // v_mfma_f32_32x32x16_{f16,bf16} products in the expanded form
 //
-//   arg = (2c y).x_i - c |x_i|^2 + (K - c |y|^2),
+//   a = (2c y).x_i - c |x_i|^2 - c |y|^2,
 //
 // with FP32 accumulation. Both factors of the two products are split into a
 // high and a low half-precision part, and three of the four cross products
 // are kept (hi*hi + hi*lo + lo*hi), which leaves a relative error of about
 // 2^-22 (f16) or 2^-16 (bf16) per term. The feature order along K is
-//   [w_hi.x_hi (D) | w_hi.x_lo (D) | w_lo.x_hi (D) | nc_hi q_hi, nc_hi q_lo, nc_lo q_hi | 0...]
+//   [w_hi.x_hi (D) | w_hi.x_lo (D) | w_lo.x_hi (D) | nc_hi q_hi, nc_hi q_lo, nc_lo q_hi | S.1 | 0...]
 // with w = 2 c y, nc = -c, q = |x|^2; the point side of every K slot is a
 // precomputed record (16 bytes per lane-half per 16 K slots), the sample side
 // is formed in registers once per (sample, SNR). The per-sample constant
-// K - c|y|^2 enters as the accumulator input, so it costs no K slot.
+// (K - c|y|^2 here, fed as the accumulator input; a rounded copy S in the
+// last slot in the first tier) carries no information: every output is a
+// difference of logarithms of the same sample's terms.
 //
 // Layout of the 32x32 accumulator (measured on gfx950): lane l holds column
 // j = l % 32 (one sample) and rows r = 8 (e / 4) + 4 (l / 32) + e % 4 for its
@@ -29,15 +34,15 @@
 // rows are the 32 samples' transmitted points (the diagonal of that tile),
 // so u = log2 S - log2 e_t uses bit-for-bit the term that entered S.
 //
-// Two tiers. The main kernel sums the FP32 terms 2^arg with the fixed shift K
+// Two tiers. The first sums the FP32 terms 2^arg with the fixed shift K
 // (window of ~150 nats of |LLR|). An item with a starved entry is left out of
-// the main kernel's sums; its tile is listed in the wave's own slots, and the
-// second-tier kernel -- launched with the same grid, each wave taking the
-// list of the same main-kernel wave in order -- re-forms those tiles' sums in
-// an FP64 frame, each term split as 2^frac(a) * 2^floor(a) (one exp2 in
-// [1, 2), one ldexp), which widens the window to ~700 nats. What is still
-// starved there takes the exact per-item path. Both kernels write per-block
-// partial sums in a fixed order, so every result is independent of timing.
+// its sums and its tile is listed in the wave's own slots; the lists are
+// gathered into one launch-wide list, and the second-tier kernel re-forms
+// those tiles' sums in an FP64 frame, each term split as
+// 2^frac(a) * 2^floor(a) (one exp2 in [1, 2), one ldexp), which widens the
+// window to ~1300 nats. What is still starved there takes the exact per-item
+// path. Both kernels write per-block partial sums in a fixed order, so every
+// result is independent of timing.
 #pragma once
 #include "device_common.h"
 
