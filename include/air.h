@@ -145,6 +145,11 @@ air_status air_sweep(air_ctx *ctx, const air_const *c, const uint32_t *tx_dev,
  * Synchronises. Returns -1 on error. */
 int64_t air_last_recomputed(air_ctx *ctx);
 
+/* Of those items, the number that needed the exact path (beyond the
+ * matrix-core forms' FP64 second-tier window, |LLR| of roughly 1300 nats; for
+ * the vector kernels every recomputed item). Synchronises. -1 on error. */
+int64_t air_last_exact(air_ctx *ctx);
+
 /* Kernel timing for measurement tools. While enabled, every call records a
  * pair of HIP events on the context's stream around each launch of its main
  * demapping kernel: the vector kernel, or the first tier of the matrix-core

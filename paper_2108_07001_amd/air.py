@@ -96,6 +96,8 @@ def load() -> ctypes.CDLL:
     lib.air_sweep.restype = ci
     lib.air_last_recomputed.argtypes = [vp]
     lib.air_last_recomputed.restype = i64
+    lib.air_last_exact.argtypes = [vp]
+    lib.air_last_exact.restype = i64
     lib.air_set_timing.argtypes = [vp, ci]
     lib.air_set_timing.restype = ci
     lib.air_kernel_time.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
@@ -195,6 +197,9 @@ class Context:
 
     def last_recomputed(self) -> int:
         return int(self.lib.air_last_recomputed(self.h))
+
+    def last_exact(self) -> int:
+        return int(self.lib.air_last_exact(self.h))
 
     def set_timing(self, enable: bool):
         self.check(self.lib.air_set_timing(self.h, 1 if enable else 0))

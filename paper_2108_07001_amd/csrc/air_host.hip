@@ -267,6 +267,7 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
   a.tx = tx;
   a.err = &ctx->call->err;
   a.recomputed = &ctx->call->recomputed;
+  a.exact = &ctx->call->exact;
   a.partials = ctx->partials;
   a.xl = fp64 ? (const void*)c->x64 : (const void*)c->x32;
   a.lab = c->lab;
@@ -536,6 +537,15 @@ air_status air_sweep(air_ctx* ctx, const air_const* c, const uint32_t* tx_dev, c
   } catch (...) {
     return fail(ctx, AIR_E_NOMEM, "host allocation failed");
   }
+}
+
+int64_t air_last_exact(air_ctx* ctx) {
+  if (!ctx) return -1;
+  DeviceGuard g(ctx->device);
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return -1;
+  CallWords w;
+  if (hipMemcpy(&w, ctx->call, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess) return -1;
+  return (int64_t)w.exact;
 }
 
 int64_t air_last_recomputed(air_ctx* ctx) {

@@ -39,7 +39,8 @@ struct DemapArgs {
   void* llr;                        // [S][N][m] LLRs (nats) or nullptr
   double* partials;                 // [S][4][gridDim.x]: sum u, sum v, sum u^2, sum v^2
   int* err;                         // set to 1 when a tx index >= M is seen
-  unsigned long long* recomputed;   // (sample, SNR) items that took the exact path
+  unsigned long long* recomputed;   // (sample, SNR) items finished outside the fast sums
+  unsigned long long* exact;        // of those, items that needed the exact path
   const void* xl;                   // M x D coordinates in label order (float or double)
   const uint32_t* lab;              // label of original point index j
   int64_t N;
@@ -270,6 +271,16 @@ __device__ __forceinline__ bool finish_item(const ExactArgs<T>& a, int64_t n, in
   return slow;
 }
 
+// log2 of a positive double through its binary exponent and an FP32 log2 of
+// the mantissa: absolute error ~2e-7, far inside every tolerance on the
+// quantities it feeds (differences of such logs), at a fraction of the cost
+// of the FP64 library routine.
+__device__ __forceinline__ double log2_wide(double x) {
+  int e;
+  const double mant = __builtin_frexp(x, &e);   // in [0.5, 1)
+  return (double)e + (double)__builtin_amdgcn_logf((float)mant);
+}
+
 // Outputs of one FP32-family item from sums in the FP64 frame 2^(a + K64)
 // (the matrix-core path's second tier). Entries below thr64 are recomputed
 // exactly relative to the nearest point r and put back in the frame by
@@ -298,7 +309,7 @@ __device__ __forceinline__ void finish_item_frame64(const ExactArgs<float>& a, i
     float y[D];
     reload_point<float, D>(in, a.sweep, xl, sigma, n, tl, y);
     base = (double)K64 - (double)c * (double)sqdist<float, D>(y, xl + (int64_t)r * D);
-    lam_tot = ::log2(total);
+    lam_tot = log2_wide(total);
   }
 #pragma unroll
   for (int i = 0; i < 2 * kMaxBits; ++i) {
@@ -306,7 +317,7 @@ __device__ __forceinline__ void finish_item_frame64(const ExactArgs<float>& a, i
       if (total_slow || !(side[i] >= thr64))
         lam[i] = base + (double)slow_rel<float, D>(in, a.sweep, xl, a.M, sigma, c, n, tl, r, i >> 1, i & 1);
       else
-        lam[i] = ::log2(side[i]);
+        lam[i] = log2_wide(side[i]);
     }
   }
   if (llr_out) {

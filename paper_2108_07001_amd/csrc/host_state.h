@@ -17,7 +17,8 @@ namespace air {
 struct CallWords {
   int err;
   int pad;
-  unsigned long long recomputed;
+  unsigned long long recomputed;   // items finished outside the first tier's sums
+  unsigned long long exact;        // of those, items that needed the exact path
 };
 }  // namespace air
 

@@ -461,9 +461,10 @@ __device__ __forceinline__ void tier1_tile(const SampleTile<D, BF>& smp, const T
 // 2^(a + K64), K64 = 1022 - m, built exactly from one FP32 exp2 of the
 // fractional part and an ldexp by the integer part. Lanes whose sample is
 // flagged finish it here, or on the exact path when even this frame starves
-// (or the sample side left the f16 range).
+// (or the sample side left the f16 range). Returns whether this lane took the
+// exact path.
 template <int D, bool BF, bool HALF>
-__device__ __forceinline__ void tier2_tile(const SampleTile<D, BF>& smp, const Tables<BF>& tb,
+__device__ __forceinline__ bool tier2_tile(const SampleTile<D, BF>& smp, const Tables<BF>& tb,
                                            const ExactArgs<float>& ex, bool has_tx, bool flagged,
                                            int j, int h, int m, int NT, int ntb, float* lout,
                                            float& u, float& v) {
@@ -511,20 +512,20 @@ __device__ __forceinline__ void tier2_tile(const SampleTile<D, BF>& smp, const T
   u = 0.f;
   v = 0.f;
   if (flagged && !st2) {
-    const double lt = ::log2(total);
+    const double lt = log2_wide(total);
     double vpart = 0.0;
 #pragma unroll
     for (int i = 0; i < kMaxBits / 2; ++i) {
       const int k = 2 * i + h;
       if (k < m) {
-        const double l0 = ::log2(h ? side[4 * i + 2] : side[4 * i]);
-        const double l1 = ::log2(h ? side[4 * i + 3] : side[4 * i + 1]);
+        const double l0 = log2_wide(h ? side[4 * i + 2] : side[4 * i]);
+        const double l1 = log2_wide(h ? side[4 * i + 3] : side[4 * i + 1]);
         if (lout) lout[k] = (float)(0.6931471805599453094 * (l0 - l1));
         if (smp.tl >= 0) vpart += lt - (((smp.tl >> k) & 1) ? l1 : l0);
       }
     }
     v = (float)pair_sum(vpart);
-    u = (float)(lt - ::log2(val64(arg_t)));
+    u = (float)(lt - log2_wide(val64(arg_t)));
   }
   // beyond the FP64 window: the starved entries take the exact path; a
   // sample side outside the f16 range leaves no usable entry, so all do
@@ -534,8 +535,10 @@ __device__ __forceinline__ void tier2_tile(const SampleTile<D, BF>& smp, const T
 #pragma unroll
       for (int i = 0; i < 2 * kMaxBits; ++i) side[i] = 0.0;
     }
-    finish_item_frame64<D>(ex, smp.n, smp.tl, total, side, thr64, K64, ::log2(val64(arg_t)), lout, u, v);
+    finish_item_frame64<D>(ex, smp.n, smp.tl, total, side, thr64, K64, log2_wide(val64(arg_t)), lout, u,
+                           v);
   }
+  return flagged && st2 && h == 0;
 }
 
 // Offsets of the per-wave tier-2 lists of SNR point s (block s): an exclusive
@@ -658,6 +661,7 @@ __global__ __launch_bounds__(256) void demap_mfma_t2(const DemapArgs a,
   unsigned long long ents = 0;          // entries b .. b + 63, lane i holding b + i
   unsigned int ss = 0;                  // and their SNR points
   unsigned long long items = 0;         // flagged samples this wave finishes
+  unsigned long long exact = 0;         // of those, the ones that needed the exact path
   for (int64_t r = 0; r < nmine; ++r) {
     const int k = (int)(r & 63);
     if (k == 0) {
@@ -688,7 +692,9 @@ __global__ __launch_bounds__(256) void demap_mfma_t2(const DemapArgs a,
     float u, v;
     ExactArgs<float> ex = exact_args<float>(a, s);
     ex.xl = tb.xl;
-    tier2_tile<D, BF, HALF>(smp, tb, ex, a.tx != nullptr, flagged, j, h, m, NT, ntb, lout, u, v);
+    const bool ex_lane = tier2_tile<D, BF, HALF>(smp, tb, ex, a.tx != nullptr, flagged, j, h, m, NT, ntb,
+                                                 lout, u, v);
+    exact += (unsigned long long)__builtin_popcountll(__ballot(ex_lane));
     if (flagged && h == 0 && smp.tl >= 0) {
       const double du = (double)u, dv = (double)v;
       au += du;
@@ -700,6 +706,7 @@ __global__ __launch_bounds__(256) void demap_mfma_t2(const DemapArgs a,
   if (s_cur >= 0) flush();
   // one count per wave: same-address atomics from every item would serialise
   if (lane == 0 && items) atomicAdd(a.recomputed, items);
+  if (lane == 0 && exact) atomicAdd(a.exact, exact);
   __syncthreads();
   for (int i = threadIdx.x; i < S * 4; i += blockDim.x) {
     double t = 0.0;

@@ -190,23 +190,23 @@ struct WideSample {
                                         bool flag_errors, const RawInput<D>& ri) {
     n = st * 32 + j;
     valid = n < p.N;
+    // table reads at an in-bounds index, unconditionally (selected afterwards),
+    // so that no lane-dependent branch surrounds them
     const bool inb = ri.t < (uint32_t)p.M;
-    const int lab = inb ? (int)tb.lab[ri.t] : 0;
-    tl = -1;
-    if (valid && p.tx) {
-      if (!inb) {
-        if (flag_errors) atomicOr(p.err, 1);
-        tl = -2;
-      } else {
-        tl = lab;
-      }
-    }
-    live = valid && tl != -2;
+    const int lab = (int)tb.lab[inb ? ri.t : 0u];
+    float xv[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) xv[d] = tb.xl[lab * D + d];
+    const bool has_t = valid && p.tx != nullptr;
+    const bool bad = has_t && !inb;
+    if (flag_errors && bad) atomicOr(p.err, 1);
+    tl = has_t ? (inb ? lab : -2) : -1;
+    live = valid && !bad;
     tq = tl >= 0 ? tl : 0;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const float zi = live ? ri.z[d] : 0.0f;
-      y[d] = (p.sweep && live) ? __builtin_fmaf(p.sigma, zi, tb.xl[lab * D + d]) : zi;
+      y[d] = p.sweep ? __builtin_fmaf(p.sigma, zi, live ? xv[d] : 0.0f) : zi;
     }
   }
 };

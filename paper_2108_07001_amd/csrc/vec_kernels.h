@@ -161,7 +161,10 @@ __global__ __launch_bounds__(kBlock) void demap_vec(const DemapArgs a, const T* 
   }
   // one count per wave: same-address atomics from every item would serialise
   const double wslow = wave_sum((double)slow_items);
-  if (lane == 0 && wslow > 0.0) atomicAdd(a.recomputed, (unsigned long long)wslow);
+  if (lane == 0 && wslow > 0.0) {
+    atomicAdd(a.recomputed, (unsigned long long)wslow);
+    atomicAdd(a.exact, (unsigned long long)wslow);
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < S * 4; i += blockDim.x) {
     double t = 0.0;

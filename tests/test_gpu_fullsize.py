@@ -1,0 +1,74 @@
+"""GPU parity at the full workload sizes, in the launch configuration bench.py
+times (one air_sweep over all samples and SNR points, fp16x3).
+
+8-PSK^2 is checked element by element against the FP64 oracle on the whole
+workload. For the two large Gaussian sets the oracle cannot run on the whole
+workload within a test, so (a) the LLRs of a random sample of received points
+are checked one by one against the oracle run on exactly those points, and
+(b) the full-size MI/GMI must equal the sample-weighted combination of two
+calls on the halves of the block (the sums are additive, so this holds at any
+size up to FP64 rounding; it catches lost or doubled tiles, lists and partial
+sums), while the per-item arithmetic behind them is what (a) and the
+small-size parity tests pin to the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2108_07001_amd import air, inputs
+from tests.helpers import assert_llr, assert_stats, to_dev, tx_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = air.Context(0)
+    yield c
+    c.close()
+
+
+def test_psk8x8_full_size_elementwise(ctx):
+    w = inputs.make("psk8x8")
+    c = ctx.const(w.X, w.labels)
+    st, L = ctx.sweep(c, tx_dev(w.tx), to_dev(w.z, torch.float32), w.snr_db, prec="fp16x3", llr=True)
+    ctx.sync()
+    ref = oracle.sweep(w.X, w.labels, w.tx, w.z, w.snr_db)
+    assert_stats(st.cpu().numpy(), ref["stats"])
+    assert_llr(L.cpu().numpy(), ref["llr"])
+    c.close()
+
+
+def _halves_consistent(ctx, c, w, st_full):
+    """Full-size MI/GMI against the N-weighted mean of the two halves' values."""
+    N = w.N
+    h = N // 2
+    parts = []
+    for lo, hi in ((0, h), (h, N)):
+        st, _ = ctx.sweep(c, tx_dev(w.tx[lo:hi]), to_dev(np.ascontiguousarray(w.z[lo:hi]), torch.float32),
+                          w.snr_db, prec="fp16x3")
+        parts.append((hi - lo, st.cpu().numpy()))
+    comb = sum(n * s[:, :2] for n, s in parts) / N
+    np.testing.assert_allclose(st_full[:, :2], comb, rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("name,nsample", [("gauss8d2048", 400), ("gauss12d4096", 150)])
+def test_large_sets_full_size_sampled(ctx, name, nsample):
+    w = inputs.make(name)
+    c = ctx.const(w.X, w.labels)
+    tx = tx_dev(w.tx)
+    z = to_dev(w.z, torch.float32)
+    st, L = ctx.sweep(c, tx, z, w.snr_db, prec="fp16x3", llr=True)
+    ctx.sync()
+    st = st.cpu().numpy()
+    idx = np.sort(np.random.default_rng(17).choice(w.N, size=nsample, replace=False))
+    got = L[:, torch.from_numpy(idx).to(L.device), :].cpu().numpy()
+    del L
+    torch.cuda.empty_cache()
+    ref = oracle.sweep(w.X, w.labels, w.tx[idx], w.z[idx], w.snr_db)
+    print(f"{name}: {nsample} sampled points x {len(w.snr_db)} SNR, "
+          f"MI {st[0, 0]:.4f}..{st[-1, 0]:.4f} bit, recomputed {ctx.last_recomputed()}")
+    assert_llr(got, ref["llr"])
+    assert np.isfinite(st).all()
+    _halves_consistent(ctx, c, w, st)
+    c.close()
