@@ -27,7 +27,7 @@ _lib = None
 
 def build(verbose: bool = False) -> str:
     """Compile ``oracle.c`` into ``liboracle.so`` (gcc, OpenMP, portable -O3)."""
-    cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", "-Wextra",
+    cmd = ["gcc", "-O3", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", "-Wextra",
            "-o", _LIB + ".tmp", _SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -60,6 +60,14 @@ def _load():
     lib.oracle_sweep.restype = ctypes.c_int
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = ctypes.c_int
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.oracle_hd.argtypes = [dp, up, ctypes.c_int, ctypes.c_int, fp, up, ctypes.c_int64, up, u64p]
+    lib.oracle_hd.restype = ctypes.c_int
+    lib.oracle_hd_sweep.argtypes = [dp, up, ctypes.c_int, ctypes.c_int, up, fp, ctypes.c_int64, dp,
+                                    ctypes.c_int, up, u64p]
+    lib.oracle_hd_sweep.restype = ctypes.c_int
+    lib.oracle_q_db.argtypes = [ctypes.c_double]
+    lib.oracle_q_db.restype = ctypes.c_double
     _lib = lib
     return lib
 
@@ -177,3 +185,60 @@ def sweep(X, labels, tx, Z, snr_db, llr: bool = True, per_sample: bool = False):
 def threads() -> int:
     """OpenMP threads the oracle library uses."""
     return _load().oracle_threads()
+
+
+def hard_decisions(X, labels, Y, tx=None):
+    """Nearest-point decisions of an FP32 block Y (readings R7, R8 of oracle.c).
+
+    Returns ``decided`` (N X rows) and, with tx, ``counts`` = [symbol errors,
+    bit errors]."""
+    X, labels = _const(X, labels)
+    M, D = X.shape
+    Y = np.ascontiguousarray(Y, dtype=np.float32)
+    if Y.ndim != 2 or Y.shape[1] != D:
+        raise OracleError("Y must be N x D")
+    N = Y.shape[0]
+    txa = None if tx is None else np.ascontiguousarray(tx, dtype=np.uint32)
+    dec = np.empty(N, dtype=np.uint32)
+    counts = np.zeros(2, dtype=np.uint64) if txa is not None else None
+    rc = _load().oracle_hd(_ptr(X, ctypes.c_double), _ptr(labels, ctypes.c_uint32), M, D,
+                           _ptr(Y, ctypes.c_float), _ptr(txa, ctypes.c_uint32), N,
+                           _ptr(dec, ctypes.c_uint32), _ptr(counts, ctypes.c_uint64))
+    if rc != 0:
+        raise OracleError(f"oracle_hd failed with code {rc}")
+    out = {"decided": dec}
+    if counts is not None:
+        out["counts"] = counts
+    return out
+
+
+def hard_decisions_sweep(X, labels, tx, Z, snr_db, decided: bool = False):
+    """Hard decisions of the SNR sweep (y = fmaf(sigma_f, z, x_t) in FP32).
+
+    Returns ``counts`` (S x 2: symbol errors, bit errors) and optionally
+    ``decided`` (S x N)."""
+    X, labels = _const(X, labels)
+    M, D = X.shape
+    txa = np.ascontiguousarray(tx, dtype=np.uint32)
+    Z = np.ascontiguousarray(Z, dtype=np.float32)
+    if Z.ndim != 2 or Z.shape != (txa.shape[0], D):
+        raise OracleError("Z must be N x D with N = len(tx)")
+    snr = np.ascontiguousarray(np.atleast_1d(snr_db), dtype=np.float64)
+    S, N = snr.shape[0], txa.shape[0]
+    counts = np.zeros((S, 2), dtype=np.uint64)
+    dec = np.empty((S, N), dtype=np.uint32) if decided else None
+    rc = _load().oracle_hd_sweep(_ptr(X, ctypes.c_double), _ptr(labels, ctypes.c_uint32), M, D,
+                                 _ptr(txa, ctypes.c_uint32), _ptr(Z, ctypes.c_float), N,
+                                 _ptr(snr, ctypes.c_double), S, _ptr(dec, ctypes.c_uint32),
+                                 _ptr(counts, ctypes.c_uint64))
+    if rc != 0:
+        raise OracleError(f"oracle_hd_sweep failed with code {rc}")
+    out = {"counts": counts}
+    if dec is not None:
+        out["decided"] = dec
+    return out
+
+
+def q_factor_db(ber: float) -> float:
+    """Q-factor in dB from a bit error rate (reading R9 of oracle.c)."""
+    return _load().oracle_q_db(float(ber))

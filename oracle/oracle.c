@@ -280,6 +280,119 @@ int oracle_sweep(const double *X, const uint32_t *labels, int M, int D,
   return rc;
 }
 
+/* ---- hard decisions (the paper's own metric) ---------------------------
+ * The paper's receiver demaps the hard decisions of its equaliser and
+ * reports the Q-factor estimated from the bit error rate, against the BER
+ * thresholds of hard-decision FEC at 6.7 % and 20 % overhead (Sections II
+ * and III). It prints neither the decision rule nor the BER-to-Q conversion;
+ * the readings:
+ *  R7 decision: the constellation point nearest to y in squared Euclidean
+ *     distance, evaluated in FP32 (the receiver processes its samples in
+ *     32-bit floating point, Section II): every coordinate an FP32 value, the
+ *     distance accumulated over d = 0..D-1 as acc = fmaf(y_d - x_d, y_d - x_d,
+ *     acc) from acc = 0, ties to the lower label. In sweep mode
+ *     y_d = fmaf(sigma_f, z_d, x_t,d) with sigma_f the FP32 rounding of sigma.
+ *  R8 errors: a symbol error when the decided point is not the transmitted
+ *     one; its bit errors are the Hamming distance between the two labels;
+ *     BER = bit errors / (N m), SER = symbol errors / N.
+ *  R9 Q-factor: Q_dB = 20 log10(sqrt(2) erfcinv(2 BER)), the Gaussian-tail
+ *     conversion (BER = erfc(Q / sqrt 2) / 2).
+ */
+
+/* Decided point (X row) for one FP32 received point (R7). */
+static int hd_decide(const float *xf, const int *pos, int M, int D, const float *y) {
+  int best = -1;
+  float bd = 0.0f;
+  for (int l = 0; l < M; ++l) {           /* labels in increasing order: ties keep the lower */
+    const float *x = xf + (size_t)pos[l] * D;
+    float acc = 0.0f;
+    for (int d = 0; d < D; ++d) {
+      const float df = y[d] - x[d];
+      acc = fmaf(df, df, acc);
+    }
+    if (best < 0 || acc < bd) { best = pos[l]; bd = acc; }
+  }
+  return best;
+}
+
+static int hamming(uint32_t a, uint32_t b) {
+  int c = 0;
+  for (uint32_t x = a ^ b; x; x >>= 1) c += (int)(x & 1u);
+  return c;
+}
+
+/* Hard decisions of a given FP32 block Y (N x D).
+ *  tx:      transmitted indices or NULL; counts [2] = symbol errors, bit
+ *           errors (needs tx; may be NULL).
+ *  decided: N decided X rows, or NULL. */
+int oracle_hd(const double *X, const uint32_t *labels, int M, int D, const float *Y,
+              const uint32_t *tx, int64_t N, uint32_t *decided, uint64_t *counts) {
+  int m = oracle_bits(labels, M, D);
+  if (m < 0 || X == NULL || Y == NULL || N < 1 || (counts && !tx)) return ORACLE_E_INVAL;
+  if (tx)
+    for (int64_t n = 0; n < N; ++n)
+      if (tx[n] >= (uint32_t)M) return ORACLE_E_INVAL;
+  float *xf = (float *)malloc(sizeof(float) * (size_t)M * D);
+  int *pos = (int *)malloc(sizeof(int) * (size_t)M);
+  if (!xf || !pos) { free(xf); free(pos); return ORACLE_E_NOMEM; }
+  for (int64_t i = 0; i < (int64_t)M * D; ++i) xf[i] = (float)X[i];
+  for (int j = 0; j < M; ++j) pos[labels[j]] = j;
+  uint64_t se = 0, be = 0;
+#pragma omp parallel for schedule(static) reduction(+ : se, be)
+  for (int64_t n = 0; n < N; ++n) {
+    const int j = hd_decide(xf, pos, M, D, Y + (size_t)n * D);
+    if (decided) decided[n] = (uint32_t)j;
+    if (tx && (uint32_t)j != tx[n]) {
+      se += 1;
+      be += (uint64_t)hamming(labels[j], labels[tx[n]]);
+    }
+  }
+  if (counts) { counts[0] = se; counts[1] = be; }
+  free(xf);
+  free(pos);
+  return ORACLE_OK;
+}
+
+/* Hard decisions of the SNR sweep: y = fmaf(sigma_f, z, x_t) in FP32 (R7).
+ * decided is S x N or NULL, counts S x 2. */
+int oracle_hd_sweep(const double *X, const uint32_t *labels, int M, int D, const uint32_t *tx,
+                    const float *Z, int64_t N, const double *snr_db, int S, uint32_t *decided,
+                    uint64_t *counts) {
+  int m = oracle_bits(labels, M, D);
+  if (m < 0 || X == NULL || tx == NULL || Z == NULL || N < 1 || snr_db == NULL || S < 1 ||
+      counts == NULL)
+    return ORACLE_E_INVAL;
+  for (int64_t n = 0; n < N; ++n)
+    if (tx[n] >= (uint32_t)M) return ORACLE_E_INVAL;
+  const double es = oracle_es(X, M, D);
+  float *y = (float *)malloc(sizeof(float) * (size_t)N * D);
+  if (!y) return ORACLE_E_NOMEM;
+  int rc = ORACLE_OK;
+  for (int s = 0; s < S && rc == ORACLE_OK; ++s) {
+    const float sf = (float)sqrt(oracle_sigma2(es, D, snr_db[s]));
+    for (int64_t n = 0; n < N; ++n)
+      for (int d = 0; d < D; ++d)
+        y[(size_t)n * D + d] = fmaf(sf, Z[(size_t)n * D + d], (float)X[(size_t)tx[n] * D + d]);
+    rc = oracle_hd(X, labels, M, D, y, tx, N, decided ? decided + (size_t)s * N : NULL, counts + 2 * s);
+  }
+  free(y);
+  return rc;
+}
+
+/* erfc^-1 by bisection on erfc (decreasing on the real line), then the
+ * Q-factor in dB of a bit error rate in (0, 0.5) (R9); NaN outside. */
+double oracle_q_db(double ber) {
+  if (!(ber > 0.0 && ber < 0.5)) return NAN;
+  const double target = 2.0 * ber;          /* erfc(x) = 2 BER, x = Q / sqrt 2 > 0 */
+  double lo = 0.0, hi = 30.0;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (erfc(mid) > target) lo = mid;
+    else hi = mid;
+  }
+  return 20.0 * log10(sqrt(2.0) * 0.5 * (lo + hi));
+}
+
 /* Number of OpenMP threads the oracle runs with (1 without OpenMP). */
 int oracle_threads(void) {
 #ifdef _OPENMP

@@ -287,3 +287,85 @@ def test_rejects_bad_arguments():
         oracle.evaluate(X, lab, np.zeros((3, 4)), 0.0, tx=np.array([0, 16, 1], dtype=np.uint32))
     with pytest.raises(oracle.OracleError):
         oracle.evaluate(X, np.zeros(16, dtype=np.uint32), np.zeros((3, 4)), 0.0)
+
+
+# ---- hard decisions, BER and Q-factor (readings R7-R9) -----------------------
+
+def _gray_qpsk():
+    """Gray-labelled QPSK: bit 0 is the sign of dimension 0, bit 1 of dimension 1."""
+    labels = np.arange(4, dtype=np.uint32)
+    X = np.array([[1 - 2 * (l & 1), 1 - 2 * ((l >> 1) & 1)] for l in range(4)],
+                 dtype=np.float64) / math.sqrt(2.0)
+    return X, labels
+
+
+@pytest.mark.parametrize("snr_db", [0.0, 4.0, 7.0])
+def test_gray_qpsk_ber_and_ser_closed_form(snr_db):
+    """Each bit of Gray QPSK is BPSK in its own dimension with amplitude^2 /
+    sigma^2 = snr (R1 with D = 2): BER = erfc(sqrt(snr / 2)) / 2 and
+    SER = 1 - (1 - BER)^2. Monte Carlo within 5 standard errors."""
+    X, labels = _gray_qpsk()
+    N = 200_000
+    tx, z = inputs.random_block(91, 4, N, 2)
+    out = oracle.hard_decisions_sweep(X, labels, tx, z, [snr_db])
+    se, be = out["counts"][0].astype(float)
+    snr = 10 ** (snr_db / 10)
+    p = 0.5 * math.erfc(math.sqrt(snr / 2.0))
+    ber, ser = be / (2 * N), se / N
+    assert abs(ber - p) <= 5 * math.sqrt(p * (1 - p) / (2 * N))
+    q = 1 - (1 - p) ** 2
+    assert abs(ser - q) <= 5 * math.sqrt(q * (1 - q) / N)
+
+
+def test_decisions_are_the_nearest_point():
+    """Against exact FP64 distances: every decision is a nearest point, and
+    differs from the FP64 argmin only at ties within FP32 rounding."""
+    X, labels = inputs.random_constellation(92, 64, 4)
+    tx, z = inputs.random_block(93, 64, 3000, 4)
+    Y = _y(X, tx, z, 8.0).astype(np.float32)
+    dec = oracle.hard_decisions(X, labels, Y)["decided"]
+    d2 = ((Y.astype(np.float64)[:, None, :] - X[None, :, :]) ** 2).sum(axis=2)
+    best = d2.min(axis=1)
+    got = d2[np.arange(len(Y)), dec]
+    assert np.all(got <= best * (1 + 1e-5) + 1e-6)
+    exact = d2.argmin(axis=1)
+    assert np.mean(dec == exact) > 0.999
+
+
+def test_decision_ties_go_to_the_lower_label():
+    X = np.array([[-1.0], [1.0]])                # the origin is equidistant
+    for labels in (np.array([0, 1], dtype=np.uint32), np.array([1, 0], dtype=np.uint32)):
+        dec = oracle.hard_decisions(X, labels, np.zeros((1, 1), np.float32))["decided"]
+        assert labels[dec[0]] == 0
+
+
+def test_bit_errors_are_label_hamming_distances():
+    X, labels = inputs.random_constellation(94, 16, 2)
+    tx, z = inputs.random_block(95, 16, 5000, 2)
+    Y = _y(X, tx, z, 3.0).astype(np.float32)
+    out = oracle.hard_decisions(X, labels, Y, tx)
+    dec = out["decided"].astype(np.int64)
+    wrong = dec != tx
+    ham = np.array([bin(int(labels[a]) ^ int(labels[b])).count("1") for a, b in zip(dec, tx)])
+    assert out["counts"][0] == wrong.sum()
+    assert out["counts"][1] == ham.sum()
+
+
+def test_hard_decision_limits():
+    X, labels = inputs.random_constellation(96, 16, 2)
+    tx, z = inputs.random_block(97, 16, 20000, 2)
+    hi = oracle.hard_decisions_sweep(X, labels, tx, z, [80.0])["counts"][0]
+    assert hi[0] == 0 and hi[1] == 0
+    # at -60 dB the decision ignores the transmitted point: SER -> 1 - 1/M
+    lo = oracle.hard_decisions_sweep(X, labels, tx, z, [-60.0])["counts"][0]
+    ser = lo[0] / len(tx)
+    assert abs(ser - (1 - 1 / 16)) < 0.02
+
+
+def test_q_factor_conversion():
+    from scipy.special import erfc
+    for q in (2.0, 3.0902323, 4.75, 7.0):
+        ber = 0.5 * erfc(q / math.sqrt(2.0))
+        assert abs(oracle.q_factor_db(ber) - 20 * math.log10(q)) < 1e-9
+    assert abs(oracle.q_factor_db(1e-3) - 9.7998) < 1e-3     # the textbook pair
+    assert math.isnan(oracle.q_factor_db(0.0)) and math.isnan(oracle.q_factor_db(0.6))
