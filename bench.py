@@ -60,6 +60,31 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def hard_decisions(ctx, c, w, tx, steps: int) -> dict:
+    """Nearest-point decisions of the same sweep (air_hard_sweep): BER, SER
+    and Q-factor per SNR point, and the decision kernel's throughput."""
+    import torch
+    z = torch.from_numpy(np.ascontiguousarray(w.z, dtype=np.float32)).to(ctx.torch_device)
+    counts, _ = ctx.hard_sweep(c, tx, z, w.snr_db)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        counts, _ = ctx.hard_sweep(c, tx, z, w.snr_db)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    from paper_2108_07001_amd import air
+    cnt = counts.cpu().numpy().astype(np.float64)
+    ber = cnt[:, 1] / (w.N * w.m)
+    ser = cnt[:, 0] / w.N
+    q = [air.q_factor_db(b) for b in ber]
+    return {"ms_per_sweep": ms,
+            "sample_points_per_s": float(w.N) * len(w.snr_db) * w.M / (ms * 1e-3),
+            "snr_db": [float(x) for x in w.snr_db], "ber": [float(x) for x in ber],
+            "ser": [float(x) for x in ser],
+            "q_db": [None if (x != x) else float(x) for x in q]}
+
+
 def serving(ctx, n_jobs: int) -> dict:
     """Replay the Poisson serving mix through the serving loop: each job is
     submitted at its arrival time and its latency runs from that time to the
@@ -268,6 +293,8 @@ def main():
         line["fp32_plain"] = {"value": pts / (f["ms"] * 1e-3), "ms_per_step": f["ms"],
                               "kernel_ms": f["kernel_ms"]}
         line["speedup_vs_fp32"] = f["ms"] / r["ms"]
+
+    line["hard_decisions"] = hard_decisions(ctx, c, w, tx, max(3, args.steps // 4))
 
     if args.serving_jobs > 0:
         line["serving"] = serving(ctx, args.serving_jobs)

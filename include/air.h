@@ -163,6 +163,39 @@ air_status air_set_timing(air_ctx *ctx, int enable);
 air_status air_kernel_time(air_ctx *ctx, double *total_ms, int64_t *launches);
 
 /* ---------------------------------------------------------------------------
+ * Hard decisions. The paper's receiver demaps the hard decisions of its
+ * equaliser and reports the Q-factor estimated from the bit error rate
+ * against hard-decision FEC thresholds (Sections II and III). The decision is
+ * the constellation point nearest to y in squared Euclidean distance, taken
+ * in FP32 as the receiver processes its samples in 32-bit floating point:
+ * acc = fma(y_d - x_d, y_d - x_d, acc) over d = 0..D-1 from 0, ties to the
+ * lower label. A symbol error is a decided point other than the transmitted
+ * one; its bit errors are the Hamming distance of the two labels.
+ * BER = bit errors / (N m), SER = symbol errors / N.
+ * ------------------------------------------------------------------------- */
+
+/* Decisions for a received block Y (float, N x D, device).
+ *  tx_dev:      N transmitted indices, or NULL (needed for counts_dev).
+ *  decided_dev: N decided X rows (uint32), or NULL.
+ *  counts_dev:  2 uint64: symbol errors, bit errors; or NULL. */
+air_status air_hard_decide(air_ctx *ctx, const air_const *c, const float *Y_dev,
+                           const uint32_t *tx_dev, int64_t N, uint32_t *decided_dev,
+                           uint64_t *counts_dev);
+
+/* Decisions over an SNR sweep, y = fma(sigma_s, z, x_t) in FP32 with sigma_s
+ * the FP32 rounding of the SNR point's noise deviation.
+ *  counts_dev:  S x 2 uint64 (symbol errors, bit errors per SNR point).
+ *  decided_dev: S x N decided X rows, or NULL. */
+air_status air_hard_sweep(air_ctx *ctx, const air_const *c, const uint32_t *tx_dev,
+                          const float *Z_dev, int64_t N, const double *snr_db_host, int S,
+                          uint64_t *counts_dev, uint32_t *decided_dev);
+
+/* Q-factor in dB of a bit error rate: 20 log10(sqrt(2) erfcinv(2 BER)), the
+ * Gaussian-tail conversion (the paper quotes Q estimated from the BER without
+ * printing the conversion). NaN unless 0 < BER < 0.5. */
+double air_q_factor_db(double ber);
+
+/* ---------------------------------------------------------------------------
  * Serving loop. Demapping jobs of uneven size (constellation, N, SNR) arrive
  * at any time, the way a software receiver hands over one buffer after
  * another (the paper streams buffers of samples to the GPU and gives each

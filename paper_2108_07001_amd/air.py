@@ -102,6 +102,12 @@ def load() -> ctypes.CDLL:
     lib.air_set_timing.restype = ci
     lib.air_kernel_time.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     lib.air_kernel_time.restype = ci
+    lib.air_hard_decide.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+    lib.air_hard_decide.restype = ci
+    lib.air_hard_sweep.argtypes = [vp, vp, vp, vp, i64, vp, ci, vp, vp]
+    lib.air_hard_sweep.restype = ci
+    lib.air_q_factor_db.argtypes = [dbl]
+    lib.air_q_factor_db.restype = dbl
     lib.air_server_create.argtypes = [vp, ctypes.c_size_t, ci, pvp]
     lib.air_server_create.restype = ci
     lib.air_server_submit.argtypes = [vp, ctypes.POINTER(AirJob), ctypes.POINTER(ctypes.c_uint64)]
@@ -272,6 +278,34 @@ class Context:
                                        PREC[prec], _ptr(stats), _ptr(L)))
         return stats, L
 
+    def hard_decide(self, c: Const, Y: torch.Tensor, tx: Optional[torch.Tensor] = None,
+                    decided: bool = True):
+        """Nearest-point decisions of a float32 block (air_hard_decide).
+        Returns (decided X rows or None, counts [symbol errors, bit errors] or None)."""
+        self._check_block(Y, c, "fp32", "Y")
+        N = Y.shape[0]
+        if tx is not None:
+            self._check_tx(tx, N)
+        dec = torch.empty(N, dtype=torch.int32, device=self.torch_device) if decided else None
+        counts = torch.empty(2, dtype=torch.int64, device=self.torch_device) if tx is not None else None
+        self.check(self.lib.air_hard_decide(self.h, c.h, _ptr(Y), _ptr(tx), N, _ptr(dec), _ptr(counts)))
+        return dec, counts
+
+    def hard_sweep(self, c: Const, tx: torch.Tensor, Z: torch.Tensor, snr_db: Sequence[float],
+                   decided: bool = False):
+        """Decisions over an SNR sweep (air_hard_sweep). Returns (counts S x 2,
+        decided S x N or None)."""
+        self._check_block(Z, c, "fp32", "Z")
+        N = Z.shape[0]
+        self._check_tx(tx, N)
+        snr = np.ascontiguousarray(np.atleast_1d(np.asarray(snr_db, dtype=np.float64)))
+        S = snr.shape[0]
+        counts = torch.empty((S, 2), dtype=torch.int64, device=self.torch_device)
+        dec = torch.empty((S, N), dtype=torch.int32, device=self.torch_device) if decided else None
+        self.check(self.lib.air_hard_sweep(self.h, c.h, _ptr(tx), _ptr(Z), N, snr.ctypes.data, S,
+                                           _ptr(counts), _ptr(dec)))
+        return counts, dec
+
     def sweep(self, c: Const, tx: torch.Tensor, Z: torch.Tensor, snr_db: Sequence[float],
               prec: str = "fp32", llr: bool = False, stats_out: Optional[torch.Tensor] = None,
               llr_out: Optional[torch.Tensor] = None):
@@ -397,6 +431,11 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def q_factor_db(ber: float) -> float:
+    """Q-factor in dB from a bit error rate (air_q_factor_db)."""
+    return float(load().air_q_factor_db(float(ber)))
 
 
 # Flat aliases with the C names.

@@ -5,6 +5,7 @@
 #include "device_common.h"
 #include "host_state.h"
 #include "mfma_wide.h"
+#include "hd_kernels.h"
 
 #include <cmath>
 #include <cstring>
@@ -39,6 +40,17 @@ static const VecFn kVecF64[kMaxD + 1] = {
     AIR_FN(f64, 11), AIR_FN(f64, 12), AIR_FN(f64, 13), AIR_FN(f64, 14), AIR_FN(f64, 15),
     AIR_FN(f64, 16)};
 #undef AIR_FN
+
+// Hard-decision launchers, one per D, defined in hd_inst.hip.
+using HdFn = hipError_t (*)(const HdArgs&, int, hipStream_t);
+#define AIR_DECL(D) hipError_t launch_hd_d##D(const HdArgs&, int, hipStream_t);
+AIR_DECL(1) AIR_DECL(2) AIR_DECL(3) AIR_DECL(4) AIR_DECL(5) AIR_DECL(6) AIR_DECL(7) AIR_DECL(8)
+AIR_DECL(9) AIR_DECL(10) AIR_DECL(11) AIR_DECL(12) AIR_DECL(13) AIR_DECL(14) AIR_DECL(15) AIR_DECL(16)
+#undef AIR_DECL
+static const HdFn kHd[kMaxD + 1] = {
+    nullptr, launch_hd_d1, launch_hd_d2, launch_hd_d3, launch_hd_d4, launch_hd_d5, launch_hd_d6,
+    launch_hd_d7, launch_hd_d8, launch_hd_d9, launch_hd_d10, launch_hd_d11, launch_hd_d12,
+    launch_hd_d13, launch_hd_d14, launch_hd_d15, launch_hd_d16};
 
 // Matrix-core launchers, one per (operand type, D), defined in mfma_inst_*.hip.
 using MfmaFn = hipError_t (*)(const DemapArgs&, const void*, int, hipStream_t, int);
@@ -123,6 +135,12 @@ __global__ __launch_bounds__(256) void finish_kernel(const double* __restrict__ 
     }
     if (s == 0 && bad) atomicOr(sticky, bad);
   }
+}
+
+// Folds a call's tx-range error into the sticky word (calls without a
+// reduction kernel of their own).
+__global__ void fold_error_kernel(const CallWords* call, int* sticky) {
+  if (threadIdx.x == 0 && call->err) atomicOr(sticky, call->err);
 }
 
 }  // namespace air
@@ -338,6 +356,63 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
   return AIR_OK;
 }
 
+// Driver of air_hard_decide / air_hard_sweep.
+air_status run_hd(air_ctx* ctx, const air_const* c, const float* in, const uint32_t* tx, int64_t N,
+                  const double* snr_db, int S, int sweep, uint32_t* decided, uint64_t* counts) {
+  if (!ctx) return AIR_E_INVAL;
+  if (!c || c->ctx != ctx) return fail(ctx, AIR_E_INVAL, "constellation is null or from another context");
+  if (!in) return fail(ctx, AIR_E_INVAL, sweep ? "Z_dev is null" : "Y_dev is null");
+  if (N < 1) return fail(ctx, AIR_E_INVAL, "N must be >= 1");
+  if (S < 1) return fail(ctx, AIR_E_INVAL, "need at least one SNR point");
+  if (counts && !tx) return fail(ctx, AIR_E_INVAL, "error counts need tx_dev");
+  if (sweep)
+    for (int s = 0; s < S; ++s)
+      if (!std::isfinite(snr_db[s])) return fail(ctx, AIR_E_INVAL, "SNR values must be finite");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, AIR_E_DEVICE, "cannot select the context's device");
+  if (!is_device_ptr(ctx, in)) return fail(ctx, AIR_E_INVAL, "input block is not device memory of this context");
+  if (tx && !is_device_ptr(ctx, tx)) return fail(ctx, AIR_E_INVAL, "tx_dev is not device memory of this context");
+  if (decided && !is_device_ptr(ctx, decided))
+    return fail(ctx, AIR_E_INVAL, "decided_dev is not device memory of this context");
+  if (counts && !is_device_ptr(ctx, counts))
+    return fail(ctx, AIR_E_INVAL, "counts_dev is not device memory of this context");
+  HdArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.in = in;
+  a.tx = tx;
+  a.xl = c->x32;
+  a.lab = c->lab;
+  a.pos = c->pos;
+  a.err = &ctx->call->err;
+  a.N = N;
+  a.M = c->M;
+  a.sweep = sweep;
+  hipError_t e = hipMemsetAsync(ctx->call, 0, sizeof(CallWords), ctx->stream);
+  if (e == hipSuccess && counts)
+    e = hipMemsetAsync(counts, 0, sizeof(uint64_t) * 2 * (size_t)S, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "clear counters");
+  const int grid = vec_grid(N);
+  for (int s0 = 0; s0 < S; s0 += kMaxSnrPerLaunch) {
+    const int ns = (S - s0 < kMaxSnrPerLaunch) ? S - s0 : kMaxSnrPerLaunch;
+    a.S = ns;
+    for (int s = 0; s < ns; ++s) {
+      double sigma = 0.0, cc = 0.0;
+      if (sweep) snr_scalars(c, snr_db[s0 + s], sigma, cc);
+      a.sigma[s] = (float)sigma;
+    }
+    a.decided = decided ? decided + (size_t)s0 * N : nullptr;
+    a.counts = counts ? reinterpret_cast<unsigned long long*>(counts) + 2 * s0 : nullptr;
+    e = kHd[c->D](a, grid, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hard-decision kernel launch");
+  }
+  // a tx-range error is reported by air_sync like the demapping calls'
+  hipLaunchKernelGGL(fold_error_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->call, ctx->sticky);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(ctx, e, "error fold launch");
+  ctx->err.clear();
+  return AIR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -476,6 +551,7 @@ air_status air_const_create(air_ctx* ctx, const double* X, const uint32_t* label
     hipError_t e = hipMalloc(&c->x64, sizeof(double) * M * D);
     if (e == hipSuccess) e = hipMalloc(&c->x32, sizeof(float) * M * D);
     if (e == hipSuccess) e = hipMalloc(&c->lab, sizeof(uint32_t) * M);
+    if (e == hipSuccess) e = hipMalloc(&c->pos, sizeof(uint32_t) * M);
     if (e == hipSuccess) e = hipMalloc(&c->rec_f16, sizeof(uint16_t) * M * kp);
     if (e == hipSuccess) e = hipMalloc(&c->rec_bf16, sizeof(uint16_t) * M * kp);
     if (e == hipSuccess) e = hipMemcpy(c->rec_f16, r16.data(), sizeof(uint16_t) * M * kp, hipMemcpyHostToDevice);
@@ -483,6 +559,10 @@ air_status air_const_create(air_ctx* ctx, const double* X, const uint32_t* label
     if (e == hipSuccess) e = hipMemcpy(c->x64, x64.data(), sizeof(double) * M * D, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->x32, x32.data(), sizeof(float) * M * D, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->lab, labels, sizeof(uint32_t) * M, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+      std::vector<uint32_t> posu(pos.begin(), pos.end());
+      e = hipMemcpy(c->pos, posu.data(), sizeof(uint32_t) * M, hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
       air_const_destroy(c);
       return hip_fail(ctx, e, "constellation upload");
@@ -501,6 +581,7 @@ void air_const_destroy(air_const* c) {
   (void)hipFree(c->x64);
   (void)hipFree(c->x32);
   (void)hipFree(c->lab);
+  (void)hipFree(c->pos);
   (void)hipFree(c->rec_f16);
   (void)hipFree(c->rec_bf16);
   delete c;
@@ -537,6 +618,45 @@ air_status air_sweep(air_ctx* ctx, const air_const* c, const uint32_t* tx_dev, c
   } catch (...) {
     return fail(ctx, AIR_E_NOMEM, "host allocation failed");
   }
+}
+
+air_status air_hard_decide(air_ctx* ctx, const air_const* c, const float* Y_dev, const uint32_t* tx_dev,
+                           int64_t N, uint32_t* decided_dev, uint64_t* counts_dev) {
+  try {
+    return run_hd(ctx, c, Y_dev, tx_dev, N, nullptr, 1, 0, decided_dev, counts_dev);
+  } catch (...) {
+    return fail(ctx, AIR_E_NOMEM, "host allocation failed");
+  }
+}
+
+air_status air_hard_sweep(air_ctx* ctx, const air_const* c, const uint32_t* tx_dev, const float* Z_dev,
+                          int64_t N, const double* snr_db_host, int S, uint64_t* counts_dev,
+                          uint32_t* decided_dev) {
+  if (ctx && (!tx_dev || !counts_dev || !snr_db_host))
+    return fail(ctx, AIR_E_INVAL, "tx_dev, counts_dev and snr_db_host must not be null");
+  try {
+    return run_hd(ctx, c, Z_dev, tx_dev, N, snr_db_host, S, 1, decided_dev, counts_dev);
+  } catch (...) {
+    return fail(ctx, AIR_E_NOMEM, "host allocation failed");
+  }
+}
+
+// erfc^-1 by Newton steps on g(x) = ln erfc(x) - ln v, which is concave and
+// decreasing: after the first step every iterate lies right of the root and
+// they decrease monotonically onto it (quadratically near it).
+double air_q_factor_db(double ber) {
+  if (!(ber > 0.0 && ber < 0.5)) return std::nan("");
+  const double lv = std::log(2.0 * ber);
+  double x = 1.0;
+  for (int it = 0; it < 200; ++it) {
+    const double e = std::erfc(x);
+    const double g = std::log(e) - lv;
+    const double dg = -1.1283791670955126 * std::exp(-x * x) / e;
+    const double step = g / dg;
+    x -= step;
+    if (std::fabs(step) <= 1e-15 * std::fabs(x)) break;
+  }
+  return 20.0 * std::log10(std::sqrt(2.0) * x);
 }
 
 int64_t air_last_exact(air_ctx* ctx) {

@@ -55,6 +55,7 @@ struct air_const {
   double* x64 = nullptr;   // M x D, label order
   float* x32 = nullptr;    // M x D, label order
   uint32_t* lab = nullptr; // label of original index j
+  uint32_t* pos = nullptr; // original index of label l
   // matrix-core point records, label order: [M][nk][2][8] operand elements
   uint16_t* rec_f16 = nullptr;
   uint16_t* rec_bf16 = nullptr;

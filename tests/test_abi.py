@@ -41,3 +41,13 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(air, "LIB_PATH", str(tmp_path / "libair.so"))
     with pytest.raises(RuntimeError):
         air.load()
+
+
+def test_q_factor_matches_oracle():
+    """air_q_factor_db is host arithmetic: checked here without a GPU."""
+    import math
+    import oracle
+    from paper_2108_07001_amd import air
+    for ber in (1e-6, 1e-4, 3.8e-3, 2e-2, 0.1, 0.3):
+        assert abs(air.q_factor_db(ber) - oracle.q_factor_db(ber)) < 1e-9
+    assert math.isnan(air.q_factor_db(0.0)) and math.isnan(air.q_factor_db(0.5))

@@ -1,0 +1,96 @@
+"""GPU hard decisions (air_hard_decide / air_hard_sweep) against the oracle.
+
+Both sides take the nearest-point decision in FP32 with the same operation
+order, so decisions and error counts are compared exactly; a differing
+decision is accepted only at a tie within FP32 rounding (checked in FP64)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2108_07001_amd import air, inputs
+from tests.helpers import to_dev, tx_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = air.Context(0)
+    yield c
+    c.close()
+
+
+def _check_decisions(X, Y, got, ref):
+    diff = np.nonzero(got != ref)[0]
+    for n in diff:                     # only ties within FP32 rounding may differ
+        y = Y[n].astype(np.float64)
+        dg = np.sum((y - X[got[n]]) ** 2)
+        dr = np.sum((y - X[ref[n]]) ** 2)
+        assert abs(dg - dr) <= 1e-5 * max(dr, 1e-6), (n, got[n], ref[n], dg, dr)
+    return len(diff)
+
+
+@pytest.mark.parametrize("name,N", [("psk8x8", 40_000), ("pmqpsk", 20_000), ("gauss8d2048", 3000)])
+def test_hard_sweep_matches_oracle(ctx, name, N):
+    w = inputs.make(name, N=N)
+    z32 = np.ascontiguousarray(w.z, dtype=np.float32)
+    c = ctx.const(w.X, w.labels)
+    counts, dec = ctx.hard_sweep(c, tx_dev(w.tx), to_dev(z32), w.snr_db, decided=True)
+    ctx.sync()
+    ref = oracle.hard_decisions_sweep(w.X, w.labels, w.tx, z32, w.snr_db, decided=True)
+    got = dec.cpu().numpy().astype(np.uint32)
+    ndiff = 0
+    for s in range(len(w.snr_db)):
+        sf = np.float32(math.sqrt(oracle.sigma2(w.X, w.snr_db[s])))
+        Y = (sf * z32 + w.X[w.tx].astype(np.float32)).astype(np.float32)
+        ndiff += _check_decisions(w.X, Y, got[s], ref["decided"][s])
+    if ndiff == 0:
+        np.testing.assert_array_equal(counts.cpu().numpy().astype(np.uint64), ref["counts"])
+    c.close()
+
+
+def test_hard_decide_given_block(ctx):
+    X, lab = inputs.random_constellation(61, 256, 4)
+    tx, z = inputs.random_block(62, 256, 5001, 4)
+    sigma = math.sqrt(oracle.sigma2(X, 11.0))
+    Y = (X[tx] + sigma * z.astype(np.float64)).astype(np.float32)
+    c = ctx.const(X, lab)
+    dec, counts = ctx.hard_decide(c, to_dev(Y), tx_dev(tx))
+    dec_only, none = ctx.hard_decide(c, to_dev(Y))
+    ctx.sync()
+    ref = oracle.hard_decisions(X, lab, Y, tx)
+    assert none is None
+    assert _check_decisions(X, Y, dec.cpu().numpy().astype(np.uint32), ref["decided"]) == 0
+    assert torch.equal(dec, dec_only)
+    np.testing.assert_array_equal(counts.cpu().numpy().astype(np.uint64), ref["counts"])
+    c.close()
+
+
+@pytest.mark.parametrize("M,D,N", [(2, 1, 1), (4, 2, 257), (16, 3, 1000), (4096, 12, 300)])
+def test_hard_decide_shapes(ctx, M, D, N):
+    X, lab = inputs.random_constellation(M + D, M, D)
+    tx, z = inputs.random_block(M * D, M, N, D)
+    Y = (X[tx] + 0.3 * z.astype(np.float64)).astype(np.float32)
+    c = ctx.const(X, lab)
+    dec, counts = ctx.hard_decide(c, to_dev(Y), tx_dev(tx))
+    ctx.sync()
+    ref = oracle.hard_decisions(X, lab, Y, tx)
+    assert _check_decisions(X, Y, dec.cpu().numpy().astype(np.uint32), ref["decided"]) == 0
+    np.testing.assert_array_equal(counts.cpu().numpy().astype(np.uint64), ref["counts"])
+    c.close()
+
+
+def test_hard_decide_invalid_tx(ctx):
+    X, lab = inputs.random_constellation(63, 16, 2)
+    tx, z = inputs.random_block(64, 16, 100, 2)
+    bad = tx.astype(np.int64).copy()
+    bad[7] = 16
+    c = ctx.const(X, lab)
+    ctx.hard_decide(c, to_dev(z.astype(np.float32)), tx_dev(bad))
+    with pytest.raises(air.AirError) as e:
+        ctx.sync()
+    assert e.value.status == air.AIR_E_RANGE
+    c.close()
