@@ -66,6 +66,10 @@ def _load():
     lib.oracle_hd_sweep.argtypes = [dp, up, ctypes.c_int, ctypes.c_int, up, fp, ctypes.c_int64, dp,
                                     ctypes.c_int, up, u64p]
     lib.oracle_hd_sweep.restype = ctypes.c_int
+    lib.oracle_eval_aux.argtypes = lib.oracle_eval.argtypes
+    lib.oracle_eval_aux.restype = ctypes.c_int
+    lib.oracle_noise_var.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, up, ctypes.c_int64, dp]
+    lib.oracle_noise_var.restype = ctypes.c_int
     lib.oracle_q_db.argtypes = [ctypes.c_double]
     lib.oracle_q_db.restype = ctypes.c_double
     _lib = lib
@@ -114,6 +118,39 @@ def evaluate(X, labels, Y, snr_db: float, tx=None, llr: bool = True, per_sample:
     Returns a dict with ``stats`` = [MI, GMI, SE_MI, SE_GMI] (bits; needs tx),
     ``llr`` (N x m, nats) and, with per_sample, ``u`` and ``v`` (bits).
     """
+    return _evaluate("oracle_eval", X, labels, Y, snr_db, tx, llr, per_sample)
+
+
+def evaluate_aux(X, labels, Y, sigma2_aux: float, tx=None, llr: bool = True,
+                 per_sample: bool = False):
+    """As evaluate, with the receiver's Gaussian metric of noise variance
+    sigma2_aux per real dimension (auxiliary channel, reading R10 of oracle.c)."""
+    return _evaluate("oracle_eval_aux", X, labels, Y, sigma2_aux, tx, llr, per_sample)
+
+
+def noise_var(X, Y, tx):
+    """Noise variance estimates with known transmitted points (reading R11):
+    D per-dimension values, then the isotropic one."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    txa = np.ascontiguousarray(tx, dtype=np.uint32)
+    M, D = X.shape
+    if Y.ndim != 2 or Y.shape != (txa.shape[0], D):
+        raise OracleError("Y must be N x D with N = len(tx)")
+    out = np.empty(D + 1)
+    rc = _load().oracle_noise_var(_ptr(X, ctypes.c_double), M, D, _ptr(Y, ctypes.c_double),
+                                  _ptr(txa, ctypes.c_uint32), Y.shape[0], _ptr(out, ctypes.c_double))
+    if rc != 0:
+        raise OracleError(f"oracle_noise_var failed with code {rc}")
+    return out
+
+
+def ngmi(gmi: float, m: int) -> float:
+    """Normalised GMI, 1 - (H(X) - GMI) / m with H(X) = m (reading R12)."""
+    return 1.0 - (m - gmi) / m
+
+
+def _evaluate(fn, X, labels, Y, noise, tx, llr, per_sample):
     X, labels = _const(X, labels)
     Y = np.ascontiguousarray(Y, dtype=np.float64)
     M, D = X.shape
@@ -129,12 +166,12 @@ def evaluate(X, labels, Y, snr_db: float, tx=None, llr: bool = True, per_sample:
     L = np.empty((N, m)) if llr else None
     u = np.empty(N) if (per_sample and txa is not None) else None
     v = np.empty(N) if (per_sample and txa is not None) else None
-    rc = _load().oracle_eval(_ptr(X, ctypes.c_double), _ptr(labels, ctypes.c_uint32), M, D,
-                             _ptr(Y, ctypes.c_double), _ptr(txa, ctypes.c_uint32), N,
-                             float(snr_db), _ptr(stats, ctypes.c_double), _ptr(L, ctypes.c_double),
-                             _ptr(u, ctypes.c_double), _ptr(v, ctypes.c_double))
+    rc = getattr(_load(), fn)(_ptr(X, ctypes.c_double), _ptr(labels, ctypes.c_uint32), M, D,
+                              _ptr(Y, ctypes.c_double), _ptr(txa, ctypes.c_uint32), N,
+                              float(noise), _ptr(stats, ctypes.c_double), _ptr(L, ctypes.c_double),
+                              _ptr(u, ctypes.c_double), _ptr(v, ctypes.c_double))
     if rc != 0:
-        raise OracleError(f"oracle_eval failed with code {rc}")
+        raise OracleError(f"{fn} failed with code {rc}")
     if stats is not None:
         out["stats"] = stats
     if L is not None:

@@ -204,16 +204,16 @@ static void fill_stats(const double *u, const double *v, int64_t N, int M, int m
  *  llr:   N x m LLRs in nats, or NULL.
  *  u, v:  per-sample MI/GMI terms (N each), or NULL.
  * Returns 0, or a negative error code for invalid arguments or no memory. */
-int oracle_eval(const double *X, const uint32_t *labels, int M, int D,
-                const double *Y, const uint32_t *tx, int64_t N, double snr_db,
-                double *stats, double *llr, double *u, double *v) {
+static int eval_sigma2(const double *X, const uint32_t *labels, int M, int D,
+                       const double *Y, const uint32_t *tx, int64_t N, double sigma2,
+                       double *stats, double *llr, double *u, double *v) {
   int m = oracle_bits(labels, M, D);
   if (m < 0 || X == NULL || Y == NULL || N < 1) return ORACLE_E_INVAL;
+  if (!(sigma2 > 0.0) || !isfinite(sigma2)) return ORACLE_E_INVAL;
   if ((stats || u || v) && tx == NULL) return ORACLE_E_INVAL;
   if (tx)
     for (int64_t n = 0; n < N; ++n)
       if (tx[n] >= (uint32_t)M) return ORACLE_E_INVAL;
-  const double sigma2 = oracle_sigma2(oracle_es(X, M, D), D, snr_db);
   double *uu = u, *vv = v, *own = NULL;
   if (tx && (!u || !v)) {
     own = (double *)malloc(sizeof(double) * 2 * (size_t)N);
@@ -243,6 +243,75 @@ int oracle_eval(const double *X, const uint32_t *labels, int M, int D,
   if (!fail && stats) fill_stats(uu, vv, N, M, m, stats);
   free(own);
   return fail ? ORACLE_E_NOMEM : ORACLE_OK;
+}
+
+int oracle_eval(const double *X, const uint32_t *labels, int M, int D,
+                const double *Y, const uint32_t *tx, int64_t N, double snr_db,
+                double *stats, double *llr, double *u, double *v) {
+  if (X == NULL || M < 1 || D < 1) return ORACLE_E_INVAL;
+  return eval_sigma2(X, labels, M, D, Y, tx, N, oracle_sigma2(oracle_es(X, M, D), D, snr_db),
+                     stats, llr, u, v);
+}
+
+/* ---- auxiliary-channel (mismatched) rates -----------------------------
+ * The paper lists NGMI among its acronyms and measures a real link, where the
+ * noise statistics are not known to the receiver. The readings:
+ *  R10 auxiliary channel: the receiver's metric is the Gaussian density
+ *      q(y|x) = N(x, sigma_a^2 I) with a caller-given sigma_a^2 (for example
+ *      the estimate of R11). LLRs, u_n, v_n, MI and GMI are those of R3 and R5
+ *      with q in place of p. With the samples drawn from the true channel,
+ *      their expectations are the mismatched-decoding rates, which are lower
+ *      bounds on the true channel's MI and GMI and equal them when sigma_a^2
+ *      is the true noise variance.
+ *  R11 noise estimate: with the transmitted points known, the per-dimension
+ *      variance is s_d^2 = (1/N) sum_n (y_nd - x_{t_n},d)^2 (the maximum-
+ *      likelihood estimate with known means, no N - 1 correction), and the
+ *      isotropic estimate is the mean of the D values.
+ *  R12 NGMI = 1 - (H(X) - GMI) / m, with H(X) = log2 M = m under the uniform
+ *      prior of R2, so NGMI = GMI / m.
+ */
+
+/* As oracle_eval, with the metric's noise variance given directly (R10). */
+int oracle_eval_aux(const double *X, const uint32_t *labels, int M, int D,
+                    const double *Y, const uint32_t *tx, int64_t N, double sigma2_aux,
+                    double *stats, double *llr, double *u, double *v) {
+  return eval_sigma2(X, labels, M, D, Y, tx, N, sigma2_aux, stats, llr, u, v);
+}
+
+/* Noise variance estimates (R11): var[d] for d < D, then the isotropic
+ * estimate var[D]. Sums are the chunked Neumaier sums of chunked_sum's kind,
+ * one per dimension, independent of the thread count. */
+int oracle_noise_var(const double *X, int M, int D, const double *Y, const uint32_t *tx,
+                     int64_t N, double *var) {
+  if (X == NULL || Y == NULL || tx == NULL || var == NULL || M < 1 || D < 1 || N < 1)
+    return ORACLE_E_INVAL;
+  for (int64_t n = 0; n < N; ++n)
+    if (tx[n] >= (uint32_t)M) return ORACLE_E_INVAL;
+  const int64_t nchunk = (N + ORACLE_CHUNK - 1) / ORACLE_CHUNK;
+  double *part = (double *)malloc(sizeof(double) * (size_t)nchunk * (size_t)D);
+  if (!part) return ORACLE_E_NOMEM;
+#pragma omp parallel for schedule(static)
+  for (int64_t q = 0; q < nchunk; ++q) {
+    const int64_t n1 = (q + 1) * ORACLE_CHUNK < N ? (q + 1) * ORACLE_CHUNK : N;
+    for (int d = 0; d < D; ++d) {
+      nsum_t acc = {0.0, 0.0};
+      for (int64_t n = q * ORACLE_CHUNK; n < n1; ++n) {
+        const double e = Y[(size_t)n * D + d] - X[(size_t)tx[n] * D + d];
+        nsum_add(&acc, e * e);
+      }
+      part[(size_t)q * D + d] = nsum_val(&acc);
+    }
+  }
+  double all = 0.0;
+  for (int d = 0; d < D; ++d) {
+    nsum_t acc = {0.0, 0.0};
+    for (int64_t q = 0; q < nchunk; ++q) nsum_add(&acc, part[(size_t)q * D + d]);
+    var[d] = nsum_val(&acc) / (double)N;
+    all += var[d];
+  }
+  var[D] = all / (double)D;
+  free(part);
+  return ORACLE_OK;
 }
 
 /* SNR sweep from unit noise (R6): for each of the S SNR points,

@@ -11,6 +11,14 @@
   both equal (number of coordinates) x C_BPSK. With the SNR reading
   snr = Es / (D sigma^2), every coordinate of PM-QPSK has s = snr.
 
+* The same input with a receiver whose Gaussian metric assumes the noise
+  variance sigma_a^2 instead of sigma^2 (mismatched decoding): by symmetry the
+  transmitted point can be fixed to +a, and
+
+      MI_aux = 1 - E_z[ log2(1 + exp(-2 a (a + sigma z) / sigma_a^2)) ],
+
+  which is at most C_BPSK, with equality at sigma_a = sigma.
+
 * Mutual information of 8-PSK (radius r, uniform input) over 2-D real AWGN by
   a Gauss-Hermite product rule; by rotational symmetry the transmitted point
   can be fixed to the first one.
@@ -51,6 +59,26 @@ def c_bpsk_gauss_hermite(snr: float, n: int = 160) -> float:
     x = -2.0 * s - 2.0 * math.sqrt(s) * z
     l1p = np.where(x > 0, x + np.log1p(np.exp(-np.abs(x))), np.log1p(np.exp(np.minimum(x, 0))))
     return 1.0 - float(np.sum(wg * l1p) / math.sqrt(math.pi) / math.log(2.0))
+
+
+def c_bpsk_aux(a: float, sigma2: float, sigma2_aux: float) -> float:
+    """Binary antipodal {+a, -a} rate (bits) under a Gaussian metric of
+    variance sigma2_aux when the true noise variance is sigma2, by adaptive
+    quadrature over z ~ N(0, 1)."""
+    sig = math.sqrt(sigma2)
+    g = 2.0 * a / sigma2_aux
+
+    def f(z):
+        x = -g * (a + sig * z)
+        l1p = x + math.log1p(math.exp(-x)) if x > 0 else math.log1p(math.exp(x))
+        return math.exp(-0.5 * z * z) / math.sqrt(2 * math.pi) * l1p / math.log(2.0)
+
+    knee = -a / sig
+    val = 0.0
+    for lo, hi in ((-np.inf, knee), (knee, 0.0 if knee < 0 else knee + 1.0), (0.0 if knee < 0 else knee + 1.0, np.inf)):
+        v, _ = integrate.quad(f, lo, hi, limit=400, epsabs=1e-14, epsrel=1e-13)
+        val += v
+    return 1.0 - val
 
 
 def mi_8psk(snr: float, radius: float = 1.0 / math.sqrt(2.0), n: int = 96) -> float:

@@ -369,3 +369,89 @@ def test_q_factor_conversion():
         assert abs(oracle.q_factor_db(ber) - 20 * math.log10(q)) < 1e-9
     assert abs(oracle.q_factor_db(1e-3) - 9.7998) < 1e-3     # the textbook pair
     assert math.isnan(oracle.q_factor_db(0.0)) and math.isnan(oracle.q_factor_db(0.6))
+
+
+# ---- auxiliary-channel rates, noise estimate, NGMI (readings R10-R12) ---------
+
+def test_aux_quadrature_reduces_to_bpsk_capacity():
+    for s_db in [0.0, 6.0]:
+        s = 10 ** (s_db / 10)
+        assert truths.c_bpsk_aux(1.0, 1.0 / s, 1.0 / s) == pytest.approx(truths.c_bpsk(s), abs=1e-9)
+        # a mismatched metric never beats the matched one
+        for r in (0.5, 0.8, 1.25, 2.0):
+            assert truths.c_bpsk_aux(1.0, 1.0 / s, r / s) < truths.c_bpsk(s)
+
+
+@pytest.mark.parametrize("ratio", [0.5, 1.0, 2.0])
+def test_aux_pmqpsk_matches_mismatched_quadrature(ratio):
+    """PM-QPSK factorises into four antipodal coordinates of amplitude 1/sqrt 2,
+    so its auxiliary-channel MI (and GMI) is four times the mismatched BPSK rate."""
+    w = inputs.make("pmqpsk", N=40_000)
+    snr_db = 4.0
+    s2 = oracle.sigma2(w.X, snr_db)
+    Y = w.X[w.tx] + math.sqrt(s2) * w.z
+    r = oracle.evaluate_aux(w.X, w.labels, Y, ratio * s2, tx=w.tx, llr=False)
+    mi, gmi, se_mi, se_gmi = r["stats"]
+    truth = 4.0 * truths.c_bpsk_aux(1.0 / math.sqrt(2.0), s2, ratio * s2)
+    assert abs(mi - truth) <= 4 * se_mi, (mi, truth, se_mi)
+    assert abs(gmi - mi) < 1e-12
+
+
+def test_aux_at_true_variance_is_the_matched_estimate():
+    w = inputs.make("psk8x8", N=3000)
+    snr_db = 7.0
+    s2 = oracle.sigma2(w.X, snr_db)
+    Y = w.X[w.tx] + math.sqrt(s2) * w.z.astype(np.float64)
+    a = oracle.evaluate(w.X, w.labels, Y, snr_db, tx=w.tx)
+    b = oracle.evaluate_aux(w.X, w.labels, Y, s2, tx=w.tx)
+    np.testing.assert_array_equal(a["stats"], b["stats"])
+    np.testing.assert_array_equal(a["llr"], b["llr"])
+
+
+def test_aux_rates_peak_at_the_true_variance():
+    """Mismatched rates are lower bounds that the true metric attains: with
+    common samples, the estimates over a grid of assumed variances peak at the
+    true one."""
+    X, lab = inputs.random_constellation(71, 16, 2)
+    tx, z = inputs.random_block(72, 16, 40_000, 2)
+    s2 = oracle.sigma2(X, 8.0)
+    Y = X[tx] + math.sqrt(s2) * z.astype(np.float64)
+    ratios = [0.6, 0.8, 1.0, 1.25, 1.6]
+    st = np.array([oracle.evaluate_aux(X, lab, Y, r * s2, tx=tx, llr=False)["stats"] for r in ratios])
+    assert int(np.argmax(st[:, 0])) == 2 and int(np.argmax(st[:, 1])) == 2
+
+
+def test_noise_var_of_a_formed_block():
+    X, lab = inputs.random_constellation(73, 64, 3)
+    tx, z = inputs.random_block(74, 64, 5000, 3)
+    z = z.astype(np.float64)
+    sigma = 0.37
+    Y = X[tx] + sigma * z
+    v = oracle.noise_var(X, Y, tx)
+    # the residuals are sigma z up to the rounding of forming Y
+    want = sigma * sigma * np.mean(z * z, axis=0)
+    np.testing.assert_allclose(v[:3], want, rtol=1e-12)
+    assert v[3] == pytest.approx(np.mean(want), rel=1e-12)
+    # sample order does not matter beyond rounding; a noiseless block gives 0
+    p = np.random.default_rng(5).permutation(5000)
+    np.testing.assert_allclose(oracle.noise_var(X, Y[p], tx[p]), v, rtol=1e-13)
+    np.testing.assert_array_equal(oracle.noise_var(X, X[tx], tx), np.zeros(4))
+    with pytest.raises(oracle.OracleError):
+        oracle.noise_var(X, Y, np.full(5000, 64, dtype=np.uint32))
+
+
+def test_ngmi():
+    assert oracle.ngmi(6.0, 6) == 1.0
+    assert oracle.ngmi(0.0, 6) == 0.0
+    assert oracle.ngmi(3.0, 4) == pytest.approx(0.75)
+    w = inputs.make("pmqpsk", N=2000)
+    r = oracle.evaluate(w.X, w.labels, _y(w.X, w.tx, w.z, 30.0), 30.0, tx=w.tx, llr=False)
+    assert oracle.ngmi(r["stats"][1], 4) == pytest.approx(1.0, abs=1e-12)
+
+
+def test_aux_rejects_bad_variance():
+    X, lab = inputs.random_constellation(75, 4, 2)
+    Y = np.zeros((3, 2))
+    for bad in (0.0, -1.0, float("inf"), float("nan")):
+        with pytest.raises(oracle.OracleError):
+            oracle.evaluate_aux(X, lab, Y, bad)
