@@ -163,6 +163,39 @@ air_status air_set_timing(air_ctx *ctx, int enable);
 air_status air_kernel_time(air_ctx *ctx, double *total_ms, int64_t *launches);
 
 /* ---------------------------------------------------------------------------
+ * Auxiliary-channel (mismatched) rates. The paper measures a real link and
+ * lists the normalised GMI among its acronyms; there the receiver does not
+ * know the noise statistics and demaps with a Gaussian model of the channel
+ * whose variance it estimates. MI and GMI computed with that metric on
+ * samples of the true channel are achievable rates of the mismatched
+ * receiver: lower bounds that equal the matched rates when the model's
+ * variance is the true one. NGMI = 1 - (H(X) - GMI) / m = GMI / m under the
+ * uniform prior.
+ * ------------------------------------------------------------------------- */
+
+/* Noise variance estimates with known transmitted points (maximum likelihood
+ * with known means, no N - 1 correction).
+ *  Y_dev:   N x D received points (double for AIR_FP64, else float).
+ *  tx_dev:  N transmitted indices into the rows of X.
+ *  var_dev: D + 1 doubles (device): (1/N) sum_n (y_nd - x_{t_n},d)^2 for each
+ *           dimension d, then their mean (the isotropic estimate). All NaN
+ *           and AIR_E_RANGE at the next air_sync if an index is >= M.
+ * Sums are FP64 in a fixed order: repeated calls give identical bits. */
+air_status air_noise_var(air_ctx *ctx, const air_const *c, const void *Y_dev,
+                         const uint32_t *tx_dev, int64_t N, air_prec prec, double *var_dev);
+
+/* air_llr and air_mi_gmi with the receiver's Gaussian metric of noise
+ * variance sigma2_aux per real dimension (> 0, finite; a host value, for
+ * example the isotropic estimate of air_noise_var) in place of the variance
+ * that an SNR point implies. Arguments, layouts and errors as air_llr /
+ * air_mi_gmi. */
+air_status air_llr_aux(air_ctx *ctx, const air_const *c, const void *Y_dev, int64_t N,
+                       double sigma2_aux, air_prec prec, void *llr_dev);
+air_status air_mi_gmi_aux(air_ctx *ctx, const air_const *c, const void *Y_dev,
+                          const uint32_t *tx_dev, int64_t N, double sigma2_aux, air_prec prec,
+                          double *stats_dev, void *llr_dev);
+
+/* ---------------------------------------------------------------------------
  * Hard decisions. The paper's receiver demaps the hard decisions of its
  * equaliser and reports the Q-factor estimated from the bit error rate
  * against hard-decision FEC thresholds (Sections II and III). The decision is

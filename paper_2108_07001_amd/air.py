@@ -102,6 +102,12 @@ def load() -> ctypes.CDLL:
     lib.air_set_timing.restype = ci
     lib.air_kernel_time.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     lib.air_kernel_time.restype = ci
+    lib.air_llr_aux.argtypes = [vp, vp, vp, i64, dbl, ci, vp]
+    lib.air_llr_aux.restype = ci
+    lib.air_mi_gmi_aux.argtypes = [vp, vp, vp, vp, i64, dbl, ci, vp, vp]
+    lib.air_mi_gmi_aux.restype = ci
+    lib.air_noise_var.argtypes = [vp, vp, vp, vp, i64, ci, vp]
+    lib.air_noise_var.restype = ci
     lib.air_hard_decide.argtypes = [vp, vp, vp, vp, i64, vp, vp]
     lib.air_hard_decide.restype = ci
     lib.air_hard_sweep.argtypes = [vp, vp, vp, vp, i64, vp, ci, vp, vp]
@@ -278,6 +284,53 @@ class Context:
                                        PREC[prec], _ptr(stats), _ptr(L)))
         return stats, L
 
+    # -- auxiliary-channel rates (air_noise_var, air_llr_aux, air_mi_gmi_aux) --
+    def noise_var(self, c: Const, Y: torch.Tensor, tx: torch.Tensor, prec: str = "fp32"):
+        """Noise variance estimates with known tx: D per-dimension values, then
+        the isotropic one (float64 tensor of D + 1, on the device)."""
+        self._check_block(Y, c, prec, "Y")
+        N = Y.shape[0]
+        self._check_tx(tx, N)
+        var = torch.empty(c.D + 1, dtype=torch.float64, device=self.torch_device)
+        self.check(self.lib.air_noise_var(self.h, c.h, _ptr(Y), _ptr(tx), N, PREC[prec], _ptr(var)))
+        return var
+
+    def llr_aux(self, c: Const, Y: torch.Tensor, sigma2_aux: float, prec: str = "fp32",
+                out: Optional[torch.Tensor] = None):
+        """LLRs with the receiver's Gaussian metric of variance sigma2_aux."""
+        self._check_block(Y, c, prec, "Y")
+        N = Y.shape[0]
+        if out is None:
+            out = torch.empty((N, c.m), dtype=self._dtype(prec), device=self.torch_device)
+        self.check(self.lib.air_llr_aux(self.h, c.h, _ptr(Y), N, float(sigma2_aux), PREC[prec],
+                                        _ptr(out)))
+        return out
+
+    def mi_gmi_aux(self, c: Const, Y: torch.Tensor, tx: torch.Tensor, sigma2_aux: float,
+                   prec: str = "fp32", llr: bool = False):
+        """MI, GMI (+ SEs) of the mismatched receiver with metric variance sigma2_aux."""
+        self._check_block(Y, c, prec, "Y")
+        N = Y.shape[0]
+        self._check_tx(tx, N)
+        stats = torch.empty(4, dtype=torch.float64, device=self.torch_device)
+        L = torch.empty((N, c.m), dtype=self._dtype(prec), device=self.torch_device) if llr else None
+        self.check(self.lib.air_mi_gmi_aux(self.h, c.h, _ptr(Y), _ptr(tx), N, float(sigma2_aux),
+                                           PREC[prec], _ptr(stats), _ptr(L)))
+        return stats, L
+
+    def aux_rates(self, c: Const, Y: torch.Tensor, tx: torch.Tensor, prec: str = "fp32"):
+        """Estimate the isotropic noise variance from (Y, tx), then the rates of
+        the receiver that demaps with it. Synchronises once (the estimate is
+        read back to form the metric). Returns a dict with sigma2, the
+        per-dimension variances, MI, GMI, their SEs and NGMI."""
+        var_dev = self.noise_var(c, Y, tx, prec)
+        self.sync()                      # the library's stream, then a plain copy
+        var = var_dev.cpu().numpy()
+        stats, _ = self.mi_gmi_aux(c, Y, tx, float(var[-1]), prec)
+        st = stats.cpu().numpy()
+        return {"sigma2": float(var[-1]), "var": var[:-1], "mi": float(st[0]), "gmi": float(st[1]),
+                "se_mi": float(st[2]), "se_gmi": float(st[3]), "ngmi": ngmi(float(st[1]), c.m)}
+
     def hard_decide(self, c: Const, Y: torch.Tensor, tx: Optional[torch.Tensor] = None,
                     decided: bool = True):
         """Nearest-point decisions of a float32 block (air_hard_decide).
@@ -445,6 +498,11 @@ def air_create(device: int = 0, stream: Optional[torch.cuda.Stream] = None) -> C
 
 def air_const_create(ctx: Context, X, labels) -> Const:
     return ctx.const(X, labels)
+
+
+def ngmi(gmi: float, m: int) -> float:
+    """Normalised GMI, 1 - (H(X) - GMI) / m with H(X) = m (uniform prior)."""
+    return 1.0 - (m - gmi) / m
 
 
 def air_llr(ctx: Context, c: Const, Y, snr_db, prec="fp32", out=None):

@@ -6,6 +6,7 @@
 #include "host_state.h"
 #include "mfma_wide.h"
 #include "hd_kernels.h"
+#include "aux_kernels.h"
 
 #include <cmath>
 #include <cstring>
@@ -207,9 +208,12 @@ void point_record(const double* x, int D, bool bf, uint16_t* out) {
 }
 
 // Per-SNR scalars of one launch.
-void fill_snr(SnrTable& t, const air_const* c, const double* snr_db, int S) {
+// With `aux`, the values are the noise variances of the receiver's Gaussian
+// metric (auxiliary channel) instead of SNR points.
+void fill_snr(SnrTable& t, const air_const* c, const double* snr_db, int S, bool aux) {
   for (int s = 0; s < S; ++s) {
-    snr_scalars(c, snr_db[s], t.sigma[s], t.c[s]);
+    if (aux) sigma2_scalars(snr_db[s], t.sigma[s], t.c[s]);
+    else snr_scalars(c, snr_db[s], t.sigma[s], t.c[s]);
     t.sigmaf[s] = (float)t.sigma[s];
     t.cf[s] = (float)t.c[s];
   }
@@ -253,15 +257,18 @@ bool prec_ok(air_prec p) { return p == AIR_FP64 || p == AIR_FP32 || p == AIR_BF1
 
 // Common driver of air_llr / air_mi_gmi / air_sweep.
 air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t* tx, int64_t N,
-               const double* snr_db, int S, int sweep, air_prec prec, double* stats, void* llr) {
+               const double* snr_db, int S, int sweep, air_prec prec, double* stats, void* llr,
+               bool aux = false) {
   if (!ctx) return AIR_E_INVAL;
   if (!c || c->ctx != ctx) return fail(ctx, AIR_E_INVAL, "constellation is null or from another context");
   if (!in) return fail(ctx, AIR_E_INVAL, sweep ? "Z_dev is null" : "Y_dev is null");
   if (N < 1) return fail(ctx, AIR_E_INVAL, "N must be >= 1");
   if (S < 1 || !snr_db) return fail(ctx, AIR_E_INVAL, "need at least one SNR point");
   if (!prec_ok(prec)) return fail(ctx, AIR_E_INVAL, "unknown precision");
-  for (int s = 0; s < S; ++s)
+  for (int s = 0; s < S; ++s) {
     if (!std::isfinite(snr_db[s])) return fail(ctx, AIR_E_INVAL, "SNR values must be finite");
+    if (aux && !(snr_db[s] > 0.0)) return fail(ctx, AIR_E_INVAL, "sigma2_aux must be positive and finite");
+  }
   if (prec == AIR_FP16X3 && !c->f16_ok)
     return fail(ctx, AIR_E_UNSUPPORTED, "constellation coordinates exceed the half-precision range");
   DeviceGuard g(ctx->device);
@@ -319,7 +326,7 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
   for (int s0 = 0; s0 < S; s0 += kMaxSnrPerLaunch) {
     const int ns = (S - s0 < kMaxSnrPerLaunch) ? S - s0 : kMaxSnrPerLaunch;
     a.S = ns;
-    fill_snr(a.snr, c, snr_db + s0, ns);
+    fill_snr(a.snr, c, snr_db + s0, ns, aux);
     a.llr = llr ? (void*)((char*)llr + (size_t)s0 * N * c->m * tsz) : nullptr;
     hipEvent_t* evp = nullptr;
     if (ctx->timing) {
@@ -409,6 +416,40 @@ air_status run_hd(air_ctx* ctx, const air_const* c, const float* in, const uint3
   hipLaunchKernelGGL(fold_error_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->call, ctx->sticky);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(ctx, e, "error fold launch");
+  ctx->err.clear();
+  return AIR_OK;
+}
+
+// Driver of air_noise_var.
+air_status run_noise_var(air_ctx* ctx, const air_const* c, const void* Y, const uint32_t* tx,
+                         int64_t N, air_prec prec, double* var) {
+  if (!ctx) return AIR_E_INVAL;
+  if (!c || c->ctx != ctx) return fail(ctx, AIR_E_INVAL, "constellation is null or from another context");
+  if (!Y || !tx || !var) return fail(ctx, AIR_E_INVAL, "Y_dev, tx_dev and var_dev must not be null");
+  if (N < 1) return fail(ctx, AIR_E_INVAL, "N must be >= 1");
+  if (!prec_ok(prec)) return fail(ctx, AIR_E_INVAL, "unknown precision");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, AIR_E_DEVICE, "cannot select the context's device");
+  if (!is_device_ptr(ctx, Y)) return fail(ctx, AIR_E_INVAL, "Y_dev is not device memory of this context");
+  if (!is_device_ptr(ctx, tx)) return fail(ctx, AIR_E_INVAL, "tx_dev is not device memory of this context");
+  if (!is_device_ptr(ctx, var)) return fail(ctx, AIR_E_INVAL, "var_dev is not device memory of this context");
+  hipError_t e = hipMemsetAsync(ctx->call, 0, sizeof(CallWords), ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "clear call words");
+  const int grid = vec_grid(N);     // <= kMaxGrid: D x grid partials fit the workspace
+  if (prec == AIR_FP64)
+    hipLaunchKernelGGL(noise_var_kernel<double>, dim3(grid), dim3(kBlock), 0, ctx->stream,
+                       static_cast<const double*>(Y), tx, c->lab, c->x64, N, c->M, c->D, ctx->partials,
+                       &ctx->call->err);
+  else
+    hipLaunchKernelGGL(noise_var_kernel<float>, dim3(grid), dim3(kBlock), 0, ctx->stream,
+                       static_cast<const float*>(Y), tx, c->lab, c->x64, N, c->M, c->D, ctx->partials,
+                       &ctx->call->err);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(ctx, e, "noise estimate launch");
+  hipLaunchKernelGGL(noise_var_finish, dim3(1), dim3(64), 0, ctx->stream, ctx->partials, grid, c->D, N,
+                     var, &ctx->call->err, ctx->sticky);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(ctx, e, "noise estimate reduction launch");
   ctx->err.clear();
   return AIR_OK;
 }
@@ -604,6 +645,35 @@ air_status air_mi_gmi(air_ctx* ctx, const air_const* c, const void* Y_dev, const
   if (ctx && (!tx_dev || !stats_dev)) return fail(ctx, AIR_E_INVAL, "tx_dev and stats_dev must not be null");
   try {
     return run(ctx, c, Y_dev, tx_dev, N, &snr_db, 1, 0, prec, stats_dev, llr_dev);
+  } catch (...) {
+    return fail(ctx, AIR_E_NOMEM, "host allocation failed");
+  }
+}
+
+air_status air_llr_aux(air_ctx* ctx, const air_const* c, const void* Y_dev, int64_t N, double sigma2_aux,
+                       air_prec prec, void* llr_dev) {
+  if (ctx && !llr_dev) return fail(ctx, AIR_E_INVAL, "llr_dev is null");
+  try {
+    return run(ctx, c, Y_dev, nullptr, N, &sigma2_aux, 1, 0, prec, nullptr, llr_dev, true);
+  } catch (...) {
+    return fail(ctx, AIR_E_NOMEM, "host allocation failed");
+  }
+}
+
+air_status air_mi_gmi_aux(air_ctx* ctx, const air_const* c, const void* Y_dev, const uint32_t* tx_dev,
+                          int64_t N, double sigma2_aux, air_prec prec, double* stats_dev, void* llr_dev) {
+  if (ctx && (!tx_dev || !stats_dev)) return fail(ctx, AIR_E_INVAL, "tx_dev and stats_dev must not be null");
+  try {
+    return run(ctx, c, Y_dev, tx_dev, N, &sigma2_aux, 1, 0, prec, stats_dev, llr_dev, true);
+  } catch (...) {
+    return fail(ctx, AIR_E_NOMEM, "host allocation failed");
+  }
+}
+
+air_status air_noise_var(air_ctx* ctx, const air_const* c, const void* Y_dev, const uint32_t* tx_dev,
+                         int64_t N, air_prec prec, double* var_dev) {
+  try {
+    return run_noise_var(ctx, c, Y_dev, tx_dev, N, prec, var_dev);
   } catch (...) {
     return fail(ctx, AIR_E_NOMEM, "host allocation failed");
   }

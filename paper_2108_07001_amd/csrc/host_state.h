@@ -108,4 +108,11 @@ inline void snr_scalars(const air_const* c, double snr_db, double& sigma, double
   cc = 1.0 / (2.0 * sigma2 * ln2);
 }
 
+// Scalars of a receiver metric with the noise variance given directly.
+inline void sigma2_scalars(double sigma2, double& sigma, double& cc) {
+  const double ln2 = 0.69314718055994530942;
+  sigma = std::sqrt(sigma2);
+  cc = 1.0 / (2.0 * sigma2 * ln2);
+}
+
 }  // namespace air

@@ -31,6 +31,9 @@ def test_create_rejects_bad_device_without_gpu_work():
     assert lib.air_llr(None, None, None, 1, 0.0, 1, None) == air.AIR_E_INVAL
     assert lib.air_mi_gmi(None, None, None, None, 1, 0.0, 1, None, None) == air.AIR_E_INVAL
     assert lib.air_sweep(None, None, None, None, 1, None, 1, 1, None, None) == air.AIR_E_INVAL
+    assert lib.air_llr_aux(None, None, None, 1, 1.0, 1, None) == air.AIR_E_INVAL
+    assert lib.air_mi_gmi_aux(None, None, None, None, 1, 1.0, 1, None, None) == air.AIR_E_INVAL
+    assert lib.air_noise_var(None, None, None, None, 1, 1, None) == air.AIR_E_INVAL
     assert lib.air_const_bits(None) == 0
     lib.air_destroy(None)
     lib.air_const_destroy(None)
