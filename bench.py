@@ -85,6 +85,52 @@ def hard_decisions(ctx, c, w, tx, steps: int) -> dict:
             "q_db": [None if (x != x) else float(x) for x in q]}
 
 
+def streaming(ctx, n_buf: int) -> dict:
+    """The paper's own formats at its buffer size: 1 GBaud 2-D M-QAM, buffers of
+    2^20 symbols pushed from pinned host memory through a 3-slot pipe
+    (air_pipe_*), LLRs back to pinned host memory. Rates are PCIe-inclusive
+    (wall clock over n_buf buffers after two warm-up buffers), beside the
+    kernels alone on device-resident buffers."""
+    import torch
+    from paper_2108_07001_amd import inputs
+    cap, snr_db, out = 1 << 20, 18.0, {}
+    for mb in range(2, 7):
+        M = 1 << mb
+        prec = "fp16x3" if M >= 16 else "fp32"
+        w = inputs.make(f"qam{M}", N=cap * n_buf)
+        sigma = math.sqrt(1.0 / (w.D * 10 ** (snr_db / 10)))      # unit-energy QAM
+        Y = torch.from_numpy((w.X[w.tx] + sigma * w.z.astype(np.float64)).astype(np.float32)).pin_memory()
+        L = torch.empty((w.N, w.m), dtype=torch.float32).pin_memory()
+        c = ctx.const(w.X, w.labels)
+        p = ctx.pipe(c, cap, depth=3, prec=prec)
+        for k in range(2):
+            p.push(Y[k * cap:(k + 1) * cap], snr_db, L[k * cap:(k + 1) * cap])
+        p.wait()
+        t0 = time.perf_counter()
+        for k in range(n_buf):
+            p.push(Y[k * cap:(k + 1) * cap], snr_db, L[k * cap:(k + 1) * cap])
+        p.wait()
+        wall = time.perf_counter() - t0
+        Yd = Y[:cap].to(ctx.torch_device)
+        Ld = torch.empty((cap, w.m), dtype=torch.float32, device=ctx.torch_device)
+        ctx.llr(c, Yd, snr_db, prec, out=Ld)
+        ctx.sync()
+        t0 = time.perf_counter()
+        for k in range(n_buf):
+            ctx.llr(c, Yd, snr_db, prec, out=Ld)
+        ctx.sync()
+        dev = time.perf_counter() - t0
+        rate = n_buf * cap / wall
+        out[f"qam{M}"] = {"prec": prec, "symbols_per_s": rate, "real_time_1GBaud": rate >= 1e9,
+                          "device_only_symbols_per_s": n_buf * cap / dev,
+                          "pcie_bytes_per_symbol": 4 * (w.D + w.m), "buffers": n_buf,
+                          "buffer_symbols": cap}
+        p.close()
+        c.close()
+        del Y, L, Yd, Ld
+    return out
+
+
 def serving(ctx, n_jobs: int) -> dict:
     """Replay the Poisson serving mix through the serving loop: each job is
     submitted at its arrival time and its latency runs from that time to the
@@ -182,6 +228,8 @@ def main():
                     help="skip timing the plain FP32 kernel beside the matrix-core form")
     ap.add_argument("--serving-jobs", type=int, default=4000,
                     help="jobs of the Poisson serving mix to replay (0: skip; full mix: 20000)")
+    ap.add_argument("--stream-buffers", type=int, default=12,
+                    help="2^20-symbol M-QAM buffers per format streamed from host memory (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device-to-device copy of 1 GiB (3 times), the "
                          "reference for scaling hardware byte counters")
@@ -295,6 +343,9 @@ def main():
         line["speedup_vs_fp32"] = f["ms"] / r["ms"]
 
     line["hard_decisions"] = hard_decisions(ctx, c, w, tx, max(3, args.steps // 4))
+
+    if args.stream_buffers > 0:
+        line["streaming"] = streaming(ctx, args.stream_buffers)
 
     if args.serving_jobs > 0:
         line["serving"] = serving(ctx, args.serving_jobs)

@@ -229,6 +229,43 @@ air_status air_hard_sweep(air_ctx *ctx, const air_const *c, const uint32_t *tx_d
 double air_q_factor_db(double ber);
 
 /* ---------------------------------------------------------------------------
+ * Per-buffer streaming from host memory. The paper's receiver moves buffers
+ * of samples to the GPU by DMA, runs each buffer on its own stream and writes
+ * the demapped results back to host memory; it is real time because buffers
+ * are processed faster than they arrive (Section II). A pipe runs each pushed
+ * buffer as H2D copy (the slot's stream) -> the air_llr kernels (the
+ * context's stream) -> D2H copy of the LLRs (the slot's stream); with
+ * `depth` slots the copies of one buffer overlap the kernels of another.
+ * Kernels of different buffers run in push order on the context's stream,
+ * and each buffer's LLRs are bitwise those of air_llr on the same data.
+ * ------------------------------------------------------------------------- */
+typedef struct air_pipe air_pipe;
+
+/* Create a pipe for buffers of at most max_symbols received symbols of the
+ * constellation c, demapped at precision prec (LLRs as air_llr).
+ * depth: 2..8 slots. Allocates, per slot, device buffers for one input and
+ * one LLR buffer and the same in pinned host staging. The pipe must be
+ * destroyed before its context; c must outlive every push. */
+air_status air_pipe_create(air_ctx *ctx, const air_const *c, int64_t max_symbols, int depth,
+                           air_prec prec, air_pipe **out);
+
+/* Queue one buffer: Y_host is N x D received symbols, llr_host receives N x m
+ * LLRs (nats), both host memory (double for AIR_FP64, else float); 1 <= N <=
+ * max_symbols. Pinned buffers (hipHostMalloc) are copied directly; pageable
+ * ones through the pipe's staging: Y_host is then read before the call
+ * returns. Returns once the buffer is queued; the oldest slot is waited for
+ * first when all are busy. llr_host (and a pinned Y_host) must stay valid
+ * and untouched until air_pipe_wait returns. */
+air_status air_pipe_push(air_pipe *p, const void *Y_host, int64_t N, double snr_db, void *llr_host);
+
+/* Wait until every pushed buffer's LLRs are in their host buffers; then
+ * air_sync on the context (reports its errors). */
+air_status air_pipe_wait(air_pipe *p);
+
+/* Release a pipe (waits for its queued work). NULL is ignored. */
+void air_pipe_destroy(air_pipe *p);
+
+/* ---------------------------------------------------------------------------
  * Serving loop. Demapping jobs of uneven size (constellation, N, SNR) arrive
  * at any time, the way a software receiver hands over one buffer after
  * another (the paper streams buffers of samples to the GPU and gives each

@@ -108,6 +108,14 @@ def load() -> ctypes.CDLL:
     lib.air_mi_gmi_aux.restype = ci
     lib.air_noise_var.argtypes = [vp, vp, vp, vp, i64, ci, vp]
     lib.air_noise_var.restype = ci
+    lib.air_pipe_create.argtypes = [vp, vp, i64, ci, ci, ctypes.POINTER(ctypes.c_void_p)]
+    lib.air_pipe_create.restype = ci
+    lib.air_pipe_push.argtypes = [vp, vp, i64, dbl, vp]
+    lib.air_pipe_push.restype = ci
+    lib.air_pipe_wait.argtypes = [vp]
+    lib.air_pipe_wait.restype = ci
+    lib.air_pipe_destroy.argtypes = [vp]
+    lib.air_pipe_destroy.restype = None
     lib.air_hard_decide.argtypes = [vp, vp, vp, vp, i64, vp, vp]
     lib.air_hard_decide.restype = ci
     lib.air_hard_sweep.argtypes = [vp, vp, vp, vp, i64, vp, ci, vp, vp]
@@ -246,6 +254,11 @@ class Context:
         sv = Server(self, budget_bytes, max_inflight)
         self._servers.add(sv)
         return sv
+
+    def pipe(self, c: Const, max_symbols: int, depth: int = 3, prec: str = "fp32") -> "Pipe":
+        pp = Pipe(self, c, max_symbols, depth, prec)
+        self._servers.add(pp)          # closed with the context, before its constellations
+        return pp
 
     def _dtype(self, prec: str):
         return torch.float64 if prec == "fp64" else torch.float32
@@ -397,6 +410,64 @@ def _buffer(x, dtype, shape, name: str, device: torch.device):
             raise AirError(AIR_E_INVAL, f"{name} must be a C-contiguous {npd.__name__} array of shape {shape}")
         return x.ctypes.data
     raise AirError(AIR_E_INVAL, f"{name} must be a tensor or numpy array")
+
+
+class Pipe:
+    """Per-buffer streaming from host memory (air_pipe_*): push() host buffers
+    of received symbols, wait() for their LLRs in host buffers. Buffers are
+    kept referenced here until wait() returns."""
+
+    def __init__(self, ctx: Context, c: Const, max_symbols: int, depth: int = 3, prec: str = "fp32"):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.c = c
+        self.prec = prec
+        self.max_symbols = int(max_symbols)
+        h = ctypes.c_void_p()
+        ctx.check(self.lib.air_pipe_create(ctx.h, c.h, self.max_symbols, int(depth), PREC[prec],
+                                           ctypes.byref(h)))
+        self.h = h
+        self._held = []
+
+    def _host(self, x, shape, name):
+        dt = np.float64 if self.prec == "fp64" else np.float32
+        if isinstance(x, torch.Tensor):
+            if x.device.type != "cpu" or x.dtype != torch.from_numpy(np.zeros(1, dt)).dtype \
+                    or tuple(x.shape) != shape or not x.is_contiguous():
+                raise AirError(AIR_E_INVAL, f"{name} must be a contiguous host {dt.__name__} tensor {shape}")
+            return x.data_ptr()
+        if not isinstance(x, np.ndarray) or x.dtype != dt or x.shape != shape or not x.flags.c_contiguous:
+            raise AirError(AIR_E_INVAL, f"{name} must be a C-contiguous {dt.__name__} array {shape}")
+        return x.ctypes.data
+
+    def push(self, Y, snr_db: float, llr):
+        """Queue one buffer: Y (N x D) and llr (N x m), host tensors (pinned or
+        not) or numpy arrays of the pipe's precision."""
+        N = int(Y.shape[0])
+        yp = self._host(Y, (N, self.c.D), "Y")
+        lp = self._host(llr, (N, self.c.m), "llr")
+        self.ctx.check(self.lib.air_pipe_push(self.h, ctypes.c_void_p(yp), N, float(snr_db),
+                                              ctypes.c_void_p(lp)))
+        self._held.append((Y, llr))
+
+    def wait(self):
+        st = self.lib.air_pipe_wait(self.h)
+        self._held.clear()
+        self.ctx.check(st)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.air_pipe_destroy(self.h)
+            self.h = None
+            self._held.clear()
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

@@ -3,8 +3,8 @@
 This module only draws inputs: constellation points, bit labels, transmitted
 indices, unit-variance noise and SNR grids (and, for the serving mix, a job
 stream). It holds none of the method's arithmetic (no symbol energies of the
-demapper, noise variances, distances or likelihoods; the only energy computed
-here is the normalisation that defines the Gaussian stand-ins) and is the one
+demapper, noise variances, distances or likelihoods; the only energies computed
+here are the normalisations that define the constellations) and is the one
 piece shared by the test oracle and the GPU path.
 
 The paper names its multidimensional formats only in its acronym list
@@ -21,6 +21,16 @@ point sets are not given, so stand-ins of the same sizes are drawn here:
 * ``gauss12d4096`` M = 4096 points i.i.d. N(0, I_12) (3 cores x 2
                   polarisations x I/Q), unit average energy, seeded-permuted
                   labels.
+
+* ``qam4`` ... ``qam64`` the paper's own 1 GBaud formats, 2-D M-QAM with
+                  M = 4, 8, 16, 32, 64 (D = 2): a product of Gray-labelled PAM
+                  levels per dimension, 2^ceil(m/2) levels in-phase and
+                  2^floor(m/2) in quadrature (square for M = 4, 16, 64,
+                  rectangular 4 x 2 and 8 x 4 for 8- and 32-QAM, whose
+                  geometry the paper does not give), label = (I label <<
+                  floor(m/2)) | Q label, unit average energy. One buffer of
+                  the paper's receiver holds 2^22 ADC samples at 4 samples per
+                  symbol, i.e. 2^20 symbols; the workload is one such buffer.
 
 Seeds: ``SeedSequence(cfg_seed).spawn(3)`` gives the (constellation + labels,
 transmitted index, noise) generators. Noise is drawn in FP64 and rounded once
@@ -47,6 +57,9 @@ CONFIGS = {
                          snr_db=[0.5 * i for i in range(41)], noise="f32",
                          desc="Gaussian 12-D M=4096, permuted labels, 41-point sweep"),
 }
+for _m in range(2, 7):
+    CONFIGS[f"qam{1 << _m}"] = dict(seed=10 + _m, M=1 << _m, D=2, N=1 << 20, snr_db=[18.0],
+                                    noise="f32", desc=f"{1 << _m}-QAM (2-D), one 2^20-symbol buffer")
 
 # Serving mix: Poisson arrivals of demap + AIR jobs.
 SERVING = dict(seed=4, rate_hz=2000.0, jobs=20_000, M_choices=(16, 64, 256, 2048),
@@ -114,6 +127,26 @@ def gaussian(rng: np.random.Generator, M: int, D: int, permuted: bool) -> tuple:
     return X, labels
 
 
+def _gray(n: int) -> int:
+    return n ^ (n >> 1)
+
+
+def qam(M: int) -> tuple:
+    """2-D M-QAM as a product of Gray-labelled PAM levels (unit average energy)."""
+    m = int(round(math.log2(M)))
+    mi, mq = (m + 1) // 2, m // 2
+    li, lq = 1 << mi, 1 << mq
+    X = np.empty((M, 2))
+    labels = np.empty(M, dtype=np.uint32)
+    for a in range(li):
+        for b in range(lq):
+            j = a * lq + b
+            X[j] = [2 * a - (li - 1), 2 * b - (lq - 1)]
+            labels[j] = (_gray(a) << mq) | _gray(b)
+    X /= math.sqrt(np.mean(np.sum(X * X, axis=1)))
+    return X, labels
+
+
 def constellation(name: str):
     """(X, labels) of a named workload (drawn from its constellation generator)."""
     cfg = CONFIGS[name]
@@ -126,6 +159,8 @@ def constellation(name: str):
         return gaussian(rc, 2048, 8, permuted=False)
     if name == "gauss12d4096":
         return gaussian(rc, 4096, 12, permuted=True)
+    if name.startswith("qam"):
+        return qam(int(name[3:]))
     raise KeyError(name)
 
 

@@ -1,0 +1,88 @@
+"""Per-buffer streaming (air_pipe_*) on the paper's 2-D M-QAM formats: every
+buffer's LLRs equal air_llr's on the same data bit for bit, and the oracle's
+within the LLR tolerance; pinned and pageable host buffers; ragged last
+buffer; two and three slots."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2108_07001_amd import air, inputs
+from tests.helpers import assert_llr, to_dev
+
+pytestmark = pytest.mark.gpu
+
+# bfloat16 splits are a characterised variant (about 2^-16 per term), held to 1e-2
+LLR_BAR = {"fp64": 1e-11, "fp32": 1e-3, "fp16x3": 1e-3, "bf16x3": 1e-2}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = air.Context(0)
+    yield c
+    c.close()
+
+
+def _buffers(M, n_buf, cap, last, snr_db, dt=np.float32):
+    w = inputs.make(f"qam{M}", N=(n_buf - 1) * cap + last)
+    s2 = oracle.sigma2(w.X, snr_db)
+    Y = (w.X[w.tx] + math.sqrt(s2) * w.z.astype(np.float64)).astype(dt)
+    bounds = [(i * cap, min((i + 1) * cap, w.N)) for i in range(n_buf)]
+    return w, Y, bounds
+
+
+@pytest.mark.parametrize("M,prec", [(4, "fp32"), (8, "fp32"), (16, "fp16x3"), (32, "fp16x3"),
+                                    (64, "fp16x3"), (64, "bf16x3"), (16, "fp64")])
+@pytest.mark.parametrize("depth,pinned", [(2, False), (3, True)])
+def test_pipe_matches_one_shot_and_oracle(ctx, M, prec, depth, pinned):
+    cap, snr_db = 4096, 14.0
+    dt = np.float64 if prec == "fp64" else np.float32
+    w, Y, bounds = _buffers(M, 5, cap, 1234, snr_db, dt)
+    c = ctx.const(w.X, w.labels)
+    p = ctx.pipe(c, cap, depth=depth, prec=prec)
+    ins, outs = [], []
+    for lo, hi in bounds:
+        if pinned:
+            yi = torch.from_numpy(np.ascontiguousarray(Y[lo:hi])).pin_memory()
+            lo_t = torch.empty((hi - lo, c.m), dtype=yi.dtype).pin_memory()
+        else:
+            yi = np.ascontiguousarray(Y[lo:hi])
+            lo_t = np.empty((hi - lo, c.m), dtype=dt)
+        ins.append(yi)
+        outs.append(lo_t)
+        p.push(yi, snr_db, lo_t)
+    p.wait()
+    ref = oracle.evaluate(w.X, w.labels, Y.astype(np.float64), snr_db, llr=True)["llr"]
+    for (lo, hi), o in zip(bounds, outs):
+        got = o.numpy() if isinstance(o, torch.Tensor) else o
+        one = ctx.llr(c, to_dev(np.ascontiguousarray(Y[lo:hi])), snr_db, prec)
+        ctx.sync()
+        np.testing.assert_array_equal(got, one.cpu().numpy())
+        assert_llr(got, ref[lo:hi], rel=LLR_BAR[prec])
+    p.close()
+    c.close()
+
+
+def test_pipe_reuse_and_errors(ctx):
+    w, Y, bounds = _buffers(16, 3, 1000, 1000, 10.0)
+    c = ctx.const(w.X, w.labels)
+    p = ctx.pipe(c, 1000, depth=2, prec="fp16x3")
+    outs = [np.empty((1000, 4), np.float32) for _ in range(6)]
+    for k in range(6):                           # more pushes than slots, twice over
+        lo, hi = bounds[k % 3]
+        p.push(np.ascontiguousarray(Y[lo:hi]), 10.0, outs[k])
+    p.wait()
+    for k in range(3):
+        np.testing.assert_array_equal(outs[k], outs[k + 3])
+    with pytest.raises(air.AirError) as e:
+        p.push(np.zeros((1001, 2), np.float32), 10.0, np.empty((1001, 4), np.float32))
+    assert e.value.status == air.AIR_E_INVAL
+    with pytest.raises(air.AirError):
+        p.push(to_dev(np.zeros((10, 2), np.float32)), 10.0, np.empty((10, 4), np.float32))
+    with pytest.raises(air.AirError) as e:
+        ctx.pipe(c, 100, depth=1)
+    assert e.value.status == air.AIR_E_INVAL
+    p.close()
+    c.close()

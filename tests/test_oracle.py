@@ -455,3 +455,26 @@ def test_aux_rejects_bad_variance():
     for bad in (0.0, -1.0, float("inf"), float("nan")):
         with pytest.raises(oracle.OracleError):
             oracle.evaluate_aux(X, lab, Y, bad)
+
+
+def test_square_qam_is_a_product_of_gray_pams():
+    """Gray square 16-/64-QAM with label (I << mq) | Q: per sample, u and v are
+    the sums of the two PAM dimensions' terms, and the LLR columns are the
+    Q-PAM's (low bits) then the I-PAM's, at any noise variance."""
+    for M in (16, 64):
+        X, lab = inputs.qam(M)
+        L = int(round(math.sqrt(M)))
+        pam = X[::L, 0:1].copy()                   # I levels, Gray labels in order of a
+        plab = np.array([a ^ (a >> 1) for a in range(L)], dtype=np.uint32)
+        tx, z = inputs.random_block(M + 1, M, 4000, 2)
+        s2 = 0.02 * (64 / M)
+        Y = X[tx] + math.sqrt(s2) * z.astype(np.float64)
+        full = oracle.evaluate_aux(X, lab, Y, s2, tx=tx, per_sample=True)
+        ti, tq = tx // L, tx % L
+        ri = oracle.evaluate_aux(pam, plab, Y[:, 0:1], s2, tx=ti, per_sample=True)
+        rq = oracle.evaluate_aux(pam, plab, Y[:, 1:2], s2, tx=tq, per_sample=True)
+        np.testing.assert_allclose(full["u"], ri["u"] + rq["u"], rtol=0, atol=1e-11)
+        np.testing.assert_allclose(full["v"], ri["v"] + rq["v"], rtol=0, atol=1e-11)
+        mq = (L.bit_length() - 1)
+        np.testing.assert_allclose(full["llr"][:, :mq], rq["llr"], rtol=1e-12, atol=1e-9)
+        np.testing.assert_allclose(full["llr"][:, mq:], ri["llr"], rtol=1e-12, atol=1e-9)
