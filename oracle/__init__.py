@@ -13,6 +13,7 @@ the readings R1-R6 stated at the top of ``oracle.c`` apply.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -66,6 +67,8 @@ def _load():
     lib.oracle_hd_sweep.argtypes = [dp, up, ctypes.c_int, ctypes.c_int, up, fp, ctypes.c_int64, dp,
                                     ctypes.c_int, up, u64p]
     lib.oracle_hd_sweep.restype = ctypes.c_int
+    lib.oracle_eval_maxlog.argtypes = lib.oracle_eval.argtypes
+    lib.oracle_eval_maxlog.restype = ctypes.c_int
     lib.oracle_eval_aux.argtypes = lib.oracle_eval.argtypes
     lib.oracle_eval_aux.restype = ctypes.c_int
     lib.oracle_noise_var.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, up, ctypes.c_int64, dp]
@@ -126,6 +129,33 @@ def evaluate_aux(X, labels, Y, sigma2_aux: float, tx=None, llr: bool = True,
     """As evaluate, with the receiver's Gaussian metric of noise variance
     sigma2_aux per real dimension (auxiliary channel, reading R10 of oracle.c)."""
     return _evaluate("oracle_eval_aux", X, labels, Y, sigma2_aux, tx, llr, per_sample)
+
+
+def evaluate_maxlog(X, labels, Y, snr_db: float, tx=None, llr: bool = True,
+                    per_sample: bool = False):
+    """Max-log demapping of Y at one SNR (readings R13, R14 of oracle.c):
+    ``llr`` (N x m, nats), ``stats`` = [NaN, GMI, NaN, SE_GMI] with tx, and
+    with per_sample ``v`` (``u`` is NaN)."""
+    return _evaluate("oracle_eval_maxlog", X, labels, Y, snr_db, tx, llr, per_sample)
+
+
+def sweep_maxlog(X, labels, tx, Z, snr_db, llr: bool = True):
+    """Max-log over an SNR sweep: y = x_t + sigma_s z formed in FP64 from Z as
+    in sweep (reading R6). Returns ``stats`` (S x 4) and ``llr`` (S x N x m)."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Z = np.asarray(Z, dtype=np.float64)
+    snr = np.atleast_1d(np.asarray(snr_db, dtype=np.float64))
+    xt = X[np.asarray(tx, dtype=np.int64)]
+    st, L = [], []
+    for s in snr:
+        r = evaluate_maxlog(X, labels, xt + math.sqrt(sigma2(X, s)) * Z, s, tx=tx, llr=llr)
+        st.append(r["stats"])
+        if llr:
+            L.append(r["llr"])
+    out = {"stats": np.array(st)}
+    if llr:
+        out["llr"] = np.array(L)
+    return out
 
 
 def noise_var(X, Y, tx):

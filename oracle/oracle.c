@@ -271,6 +271,83 @@ int oracle_eval(const double *X, const uint32_t *labels, int M, int D,
  *      prior of R2, so NGMI = GMI / m.
  */
 
+/* ---- max-log demapping ------------------------------------------------
+ * A standard receiver simplification: each bit side's log-sum-exp is replaced
+ * by its largest term. The readings:
+ *  R13 max-log LLR: L_k = min_{j: b_k(j)=1} |y - x_j|^2 / (2 sigma^2)
+ *                       - min_{j: b_k(j)=0} |y - x_j|^2 / (2 sigma^2), nats.
+ *  R14 max-log GMI: the BMD rate of a receiver that takes these LLRs as exact,
+ *      v_n = sum_k log2(1 + exp(-(1 - 2 b_k(t_n)) L_nk)), GMI = m - mean(v),
+ *      SE as R5. With the exact LLRs of R3 this is R5's v; with max-log LLRs
+ *      it is an achievable rate of that receiver (a lower bound on its GMI).
+ *      No symbol-wise MI is defined: MI, its SE and u are NaN.
+ */
+
+/* log2(1 + e^x) without overflow. */
+static double log2_1p_exp(double x) {
+  return (x > 0.0 ? x + log1p(exp(-x)) : log1p(exp(x))) / log(2.0);
+}
+
+static void maxlog_one(const double *X, const uint32_t *labels, int M, int D, int m,
+                       const double *y, double sigma2, int64_t t, double *dmin,
+                       double *llr, double *v) {
+  for (int k = 0; k < 2 * m; ++k) dmin[k] = INFINITY;
+  for (int j = 0; j < M; ++j) {
+    double d2 = 0.0;
+    for (int d = 0; d < D; ++d) {
+      double diff = y[d] - X[(size_t)j * D + d];
+      d2 += diff * diff;
+    }
+    for (int k = 0; k < m; ++k) {
+      double *slot = &dmin[2 * k + ((labels[j] >> k) & 1u)];
+      if (d2 < *slot) *slot = d2;
+    }
+  }
+  double acc = 0.0;
+  for (int k = 0; k < m; ++k) {
+    const double L = (dmin[2 * k + 1] - dmin[2 * k]) / (2.0 * sigma2);
+    if (llr) llr[k] = L;
+    if (t >= 0) acc += log2_1p_exp(-(1.0 - 2.0 * (double)((labels[t] >> k) & 1u)) * L);
+  }
+  if (t >= 0) *v = acc;
+}
+
+/* Max-log demapping of a given block at one SNR (R13, R14); arguments as
+ * oracle_eval; stats[0], stats[2] and u are NaN. */
+int oracle_eval_maxlog(const double *X, const uint32_t *labels, int M, int D,
+                       const double *Y, const uint32_t *tx, int64_t N, double snr_db,
+                       double *stats, double *llr, double *u, double *v) {
+  int m = oracle_bits(labels, M, D);
+  if (m < 0 || X == NULL || Y == NULL || N < 1 || !isfinite(snr_db)) return ORACLE_E_INVAL;
+  if ((stats || u || v) && tx == NULL) return ORACLE_E_INVAL;
+  if (tx)
+    for (int64_t n = 0; n < N; ++n)
+      if (tx[n] >= (uint32_t)M) return ORACLE_E_INVAL;
+  const double sigma2 = oracle_sigma2(oracle_es(X, M, D), D, snr_db);
+  double *vv = v, *own = NULL;
+  if (tx && !v) {
+    own = (double *)malloc(sizeof(double) * (size_t)N);
+    if (!own) return ORACLE_E_NOMEM;
+    vv = own;
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t n = 0; n < N; ++n) {
+    double dmin[2 * 12];
+    double dv = 0.0;
+    maxlog_one(X, labels, M, D, m, Y + (size_t)n * D, sigma2, tx ? (int64_t)tx[n] : -1, dmin,
+               llr ? llr + (size_t)n * m : NULL, &dv);
+    if (tx) vv[n] = dv;
+    if (u) u[n] = NAN;
+  }
+  if (stats) {
+    fill_stats(vv, vv, N, M, m, stats);
+    stats[0] = NAN;
+    stats[2] = NAN;
+  }
+  free(own);
+  return ORACLE_OK;
+}
+
 /* As oracle_eval, with the metric's noise variance given directly (R10). */
 int oracle_eval_aux(const double *X, const uint32_t *labels, int M, int D,
                     const double *Y, const uint32_t *tx, int64_t N, double sigma2_aux,

@@ -478,3 +478,65 @@ def test_square_qam_is_a_product_of_gray_pams():
         mq = (L.bit_length() - 1)
         np.testing.assert_allclose(full["llr"][:, :mq], rq["llr"], rtol=1e-12, atol=1e-9)
         np.testing.assert_allclose(full["llr"][:, mq:], ri["llr"], rtol=1e-12, atol=1e-9)
+
+
+# ---- max-log demapping (readings R13, R14) -----------------------------------
+
+def test_maxlog_equals_exact_where_each_side_has_one_dominant_structure():
+    """Any two-point set has one point per bit side, and Gray QPSK factorises
+    per dimension, so in both the max-log LLRs are the exact ones."""
+    for X, lab in (inputs.random_constellation(81, 2, 3), _gray_qpsk()):
+        M, D = X.shape
+        tx, z = inputs.random_block(82 + M, M, 3000, D)
+        Y = _y(X, tx, z, 6.0)
+        a = oracle.evaluate(X, lab, Y, 6.0, tx=tx)
+        b = oracle.evaluate_maxlog(X, lab, Y, 6.0, tx=tx)
+        np.testing.assert_allclose(b["llr"], a["llr"], rtol=1e-12, atol=1e-12)
+        assert b["stats"][1] == pytest.approx(a["stats"][1], abs=1e-12)
+        assert math.isnan(b["stats"][0]) and math.isnan(b["stats"][2])
+
+
+@pytest.mark.parametrize("name", ["psk8x8", "gauss8d2048"])
+def test_maxlog_within_log_side_size_of_exact(name):
+    """Each side's log-sum-exp lies in [max, max + ln(M/2)], so every max-log
+    LLR is within ln(M/2) nats of the exact one; the max-log GMI (a mismatched
+    rate) does not exceed the exact GMI beyond sampling noise."""
+    w = inputs.make(name, N=1500)
+    for snr_db in (w.snr_db[0], w.snr_db[len(w.snr_db) // 2], w.snr_db[-1]):
+        Y = _y(w.X, w.tx, w.z, snr_db)
+        a = oracle.evaluate(w.X, w.labels, Y, snr_db, tx=w.tx, per_sample=True)
+        b = oracle.evaluate_maxlog(w.X, w.labels, Y, snr_db, tx=w.tx, per_sample=True)
+        assert np.max(np.abs(b["llr"] - a["llr"])) <= math.log(w.M / 2) + 1e-9
+        d = b["v"] - a["v"]
+        assert np.mean(d) >= -4 * np.std(d) / math.sqrt(len(d))
+        assert np.isnan(b["u"]).all()
+
+
+def test_maxlog_brute_force_tiny():
+    """Direct minimum distances per bit side, written out per sample."""
+    X, lab = inputs.random_constellation(83, 8, 2)
+    tx, z = inputs.random_block(84, 8, 200, 2)
+    snr_db = 9.0
+    Y = _y(X, tx, z, snr_db)
+    s2 = oracle.sigma2(X, snr_db)
+    r = oracle.evaluate_maxlog(X, lab, Y, snr_db, tx=tx, per_sample=True)
+    for n in range(len(tx)):
+        d = [float(np.sum((Y[n] - X[j]) ** 2)) for j in range(8)]
+        vn = 0.0
+        for k in range(3):
+            d0 = min(d[j] for j in range(8) if not (lab[j] >> k) & 1)
+            d1 = min(d[j] for j in range(8) if (lab[j] >> k) & 1)
+            L = (d1 - d0) / (2 * s2)
+            assert r["llr"][n, k] == pytest.approx(L, rel=1e-12, abs=1e-12)
+            sgn = 1.0 if not (lab[tx[n]] >> k) & 1 else -1.0
+            vn += math.log1p(math.exp(-sgn * L)) / LN2 if -sgn * L < 30 else -sgn * L / LN2
+        assert r["v"][n] == pytest.approx(vn, rel=1e-10, abs=1e-12)
+
+
+def test_maxlog_high_snr_limit_and_sweep():
+    w = inputs.make("psk8x8", N=2000, snr_db=[40.0])
+    r = oracle.sweep_maxlog(w.X, w.labels, w.tx, w.z, w.snr_db)
+    assert r["stats"][0, 1] == pytest.approx(6.0, abs=1e-9)
+    Y = w.X[w.tx] + math.sqrt(oracle.sigma2(w.X, 40.0)) * w.z.astype(np.float64)
+    e = oracle.evaluate_maxlog(w.X, w.labels, Y, 40.0, tx=w.tx)
+    np.testing.assert_array_equal(r["llr"][0], e["llr"])
