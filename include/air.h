@@ -196,6 +196,27 @@ air_status air_mi_gmi_aux(air_ctx *ctx, const air_const *c, const void *Y_dev,
                           double *stats_dev, void *llr_dev);
 
 /* ---------------------------------------------------------------------------
+ * Max-log demapping, the usual receiver simplification of soft demapping:
+ * each bit side's log-sum-exp is replaced by its largest term, so that
+ *   L_k = min_{j: b_k(j)=1} |y - x_j|^2 / (2 sigma^2)
+ *       - min_{j: b_k(j)=0} |y - x_j|^2 / (2 sigma^2)   (nats),
+ * with no exponentials or logarithms per point. Its GMI is the bit-metric
+ * rate of a receiver that takes these LLRs as exact:
+ *   GMI = m - mean_n sum_k log2(1 + exp(-(1 - 2 b_k(t_n)) L_nk)),
+ * an achievable rate of that receiver (no more than the exact GMI). No
+ * symbol-wise MI is defined: stats[0] (MI) and stats[2] (SE_MI) are NaN.
+ * Precisions, layouts and errors as air_llr / air_mi_gmi / air_sweep.
+ * ------------------------------------------------------------------------- */
+air_status air_llr_maxlog(air_ctx *ctx, const air_const *c, const void *Y_dev, int64_t N,
+                          double snr_db, air_prec prec, void *llr_dev);
+air_status air_gmi_maxlog(air_ctx *ctx, const air_const *c, const void *Y_dev,
+                          const uint32_t *tx_dev, int64_t N, double snr_db, air_prec prec,
+                          double *stats_dev, void *llr_dev);
+air_status air_sweep_maxlog(air_ctx *ctx, const air_const *c, const uint32_t *tx_dev,
+                            const void *Z_dev, int64_t N, const double *snr_db_host, int S,
+                            air_prec prec, double *stats_dev, void *llr_dev);
+
+/* ---------------------------------------------------------------------------
  * Hard decisions. The paper's receiver demaps the hard decisions of its
  * equaliser and reports the Q-factor estimated from the bit error rate
  * against hard-decision FEC thresholds (Sections II and III). The decision is

@@ -102,6 +102,12 @@ def load() -> ctypes.CDLL:
     lib.air_set_timing.restype = ci
     lib.air_kernel_time.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     lib.air_kernel_time.restype = ci
+    lib.air_llr_maxlog.argtypes = [vp, vp, vp, i64, dbl, ci, vp]
+    lib.air_llr_maxlog.restype = ci
+    lib.air_gmi_maxlog.argtypes = [vp, vp, vp, vp, i64, dbl, ci, vp, vp]
+    lib.air_gmi_maxlog.restype = ci
+    lib.air_sweep_maxlog.argtypes = [vp, vp, vp, vp, i64, vp, ci, ci, vp, vp]
+    lib.air_sweep_maxlog.restype = ci
     lib.air_llr_aux.argtypes = [vp, vp, vp, i64, dbl, ci, vp]
     lib.air_llr_aux.restype = ci
     lib.air_mi_gmi_aux.argtypes = [vp, vp, vp, vp, i64, dbl, ci, vp, vp]
@@ -372,9 +378,38 @@ class Context:
                                            _ptr(counts), _ptr(dec)))
         return counts, dec
 
+    # -- max-log form (air_llr_maxlog, air_gmi_maxlog, air_sweep_maxlog) -------
+    def llr_maxlog(self, c: Const, Y: torch.Tensor, snr_db: float, prec: str = "fp32",
+                   out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._check_block(Y, c, prec, "Y")
+        N = Y.shape[0]
+        if out is None:
+            out = torch.empty((N, c.m), dtype=self._dtype(prec), device=self.torch_device)
+        elif out.shape != (N, c.m) or out.dtype != self._dtype(prec) or not out.is_contiguous():
+            raise AirError(AIR_E_INVAL, "out has the wrong shape or dtype")
+        self.check(self.lib.air_llr_maxlog(self.h, c.h, _ptr(Y), N, float(snr_db), PREC[prec], _ptr(out)))
+        return out
+
+    def gmi_maxlog(self, c: Const, Y: torch.Tensor, tx: torch.Tensor, snr_db: float,
+                   prec: str = "fp32", llr: bool = False):
+        """[NaN, GMI, NaN, SE_GMI] of the max-log receiver, and optionally its LLRs."""
+        self._check_block(Y, c, prec, "Y")
+        N = Y.shape[0]
+        self._check_tx(tx, N)
+        stats = torch.empty(4, dtype=torch.float64, device=self.torch_device)
+        L = torch.empty((N, c.m), dtype=self._dtype(prec), device=self.torch_device) if llr else None
+        self.check(self.lib.air_gmi_maxlog(self.h, c.h, _ptr(Y), _ptr(tx), N, float(snr_db),
+                                           PREC[prec], _ptr(stats), _ptr(L)))
+        return stats, L
+
+    def sweep_maxlog(self, c: Const, tx: torch.Tensor, Z: torch.Tensor, snr_db: Sequence[float],
+                     prec: str = "fp32", llr: bool = False, stats_out: Optional[torch.Tensor] = None,
+                     llr_out: Optional[torch.Tensor] = None):
+        return self.sweep(c, tx, Z, snr_db, prec, llr, stats_out, llr_out, _fn="air_sweep_maxlog")
+
     def sweep(self, c: Const, tx: torch.Tensor, Z: torch.Tensor, snr_db: Sequence[float],
               prec: str = "fp32", llr: bool = False, stats_out: Optional[torch.Tensor] = None,
-              llr_out: Optional[torch.Tensor] = None):
+              llr_out: Optional[torch.Tensor] = None, _fn: str = "air_sweep"):
         self._check_block(Z, c, prec, "Z")
         N = Z.shape[0]
         self._check_tx(tx, N)
@@ -389,8 +424,8 @@ class Context:
             L = torch.empty((S, N, c.m), dtype=self._dtype(prec), device=self.torch_device)
         if L is not None and (L.shape != (S, N, c.m) or L.dtype != self._dtype(prec)):
             raise AirError(AIR_E_INVAL, "llr_out has the wrong shape or dtype")
-        self.check(self.lib.air_sweep(self.h, c.h, _ptr(tx), _ptr(Z), N, snr.ctypes.data, S,
-                                      PREC[prec], _ptr(stats), _ptr(L)))
+        self.check(getattr(self.lib, _fn)(self.h, c.h, _ptr(tx), _ptr(Z), N, snr.ctypes.data, S,
+                                          PREC[prec], _ptr(stats), _ptr(L)))
         return stats, L
 
 

@@ -17,8 +17,8 @@
 namespace air {
 
 // Vector-kernel launchers, one per (type, D), defined in vec_inst_*.hip.
-using VecFn = hipError_t (*)(const DemapArgs&, int, hipStream_t);
-#define AIR_DECL(tag, D) hipError_t launch_vec_##tag##_d##D(const DemapArgs&, int, hipStream_t);
+using VecFn = hipError_t (*)(const DemapArgs&, int, hipStream_t, bool);
+#define AIR_DECL(tag, D) hipError_t launch_vec_##tag##_d##D(const DemapArgs&, int, hipStream_t, bool);
 #define AIR_DECL_ALL(tag)                                                                        \
   AIR_DECL(tag, 1) AIR_DECL(tag, 2) AIR_DECL(tag, 3) AIR_DECL(tag, 4) AIR_DECL(tag, 5)          \
   AIR_DECL(tag, 6) AIR_DECL(tag, 7) AIR_DECL(tag, 8) AIR_DECL(tag, 9) AIR_DECL(tag, 10)         \
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const double* __restrict__ 
                                                      const double* __restrict__ t2_partials,
                                                      int nblocks, int nblocks2, int64_t N, int M, int m,
                                                      double* stats, const CallWords* call,
-                                                     int* sticky) {
+                                                     int* sticky, int no_mi) {
   __shared__ double sums[4];
   const int s = blockIdx.x;
   const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -128,6 +128,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const double* __restrict__ 
         se_mi = sqrt((vu > 0.0 ? vu : 0.0) / n);
         se_gmi = sqrt((vv > 0.0 ? vv : 0.0) / n);
       }
+      if (no_mi) mi = se_mi = __builtin_nan("");       // max-log: no symbol-wise MI
       if (bad) mi = gmi = se_mi = se_gmi = __builtin_nan("");
       stats[4 * s + 0] = mi;
       stats[4 * s + 1] = gmi;
@@ -258,7 +259,7 @@ bool prec_ok(air_prec p) { return p == AIR_FP64 || p == AIR_FP32 || p == AIR_BF1
 // Common driver of air_llr / air_mi_gmi / air_sweep.
 air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t* tx, int64_t N,
                const double* snr_db, int S, int sweep, air_prec prec, double* stats, void* llr,
-               bool aux = false) {
+               bool aux = false, bool maxlog = false) {
   if (!ctx) return AIR_E_INVAL;
   if (!c || c->ctx != ctx) return fail(ctx, AIR_E_INVAL, "constellation is null or from another context");
   if (!in) return fail(ctx, AIR_E_INVAL, sweep ? "Z_dev is null" : "Y_dev is null");
@@ -343,19 +344,20 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
       e = hipEventRecord(evp[0], ctx->stream);
       if (e != hipSuccess) return hip_fail(ctx, e, "timing event record");
     }
-    e = mfma ? mfn(a, rec, grid, ctx->stream, 0) : vfn(a, grid, ctx->stream);
+    e = mfma ? mfn(a, rec, grid, ctx->stream, maxlog ? 2 : 0) : vfn(a, grid, ctx->stream, maxlog);
     if (e != hipSuccess) return hip_fail(ctx, e, "demapping kernel launch");
     if (evp) {
       e = hipEventRecord(evp[1], ctx->stream);
       if (e != hipSuccess) return hip_fail(ctx, e, "timing event record");
     }
-    if (mfma) {
+    const bool tier2 = mfma && !maxlog;
+    if (tier2) {
       e = mfn(a, rec, grid, ctx->stream, 1);
       if (e != hipSuccess) return hip_fail(ctx, e, "second-tier launch");
     }
     hipLaunchKernelGGL(finish_kernel, dim3(ns), dim3(256), 0, ctx->stream, ctx->partials,
-                       mfma ? ctx->t2_partials : nullptr, grid, t2_grid(grid), N, c->M, c->m,
-                       stats ? stats + 4 * s0 : nullptr, ctx->call, ctx->sticky);
+                       tier2 ? ctx->t2_partials : nullptr, grid, t2_grid(grid), N, c->M, c->m,
+                       stats ? stats + 4 * s0 : nullptr, ctx->call, ctx->sticky, maxlog ? 1 : 0);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "reduction kernel launch");
   }
@@ -665,6 +667,37 @@ air_status air_mi_gmi_aux(air_ctx* ctx, const air_const* c, const void* Y_dev, c
   if (ctx && (!tx_dev || !stats_dev)) return fail(ctx, AIR_E_INVAL, "tx_dev and stats_dev must not be null");
   try {
     return run(ctx, c, Y_dev, tx_dev, N, &sigma2_aux, 1, 0, prec, stats_dev, llr_dev, true);
+  } catch (...) {
+    return fail(ctx, AIR_E_NOMEM, "host allocation failed");
+  }
+}
+
+air_status air_llr_maxlog(air_ctx* ctx, const air_const* c, const void* Y_dev, int64_t N, double snr_db,
+                          air_prec prec, void* llr_dev) {
+  if (ctx && !llr_dev) return fail(ctx, AIR_E_INVAL, "llr_dev is null");
+  try {
+    return run(ctx, c, Y_dev, nullptr, N, &snr_db, 1, 0, prec, nullptr, llr_dev, false, true);
+  } catch (...) {
+    return fail(ctx, AIR_E_NOMEM, "host allocation failed");
+  }
+}
+
+air_status air_gmi_maxlog(air_ctx* ctx, const air_const* c, const void* Y_dev, const uint32_t* tx_dev,
+                          int64_t N, double snr_db, air_prec prec, double* stats_dev, void* llr_dev) {
+  if (ctx && (!tx_dev || !stats_dev)) return fail(ctx, AIR_E_INVAL, "tx_dev and stats_dev must not be null");
+  try {
+    return run(ctx, c, Y_dev, tx_dev, N, &snr_db, 1, 0, prec, stats_dev, llr_dev, false, true);
+  } catch (...) {
+    return fail(ctx, AIR_E_NOMEM, "host allocation failed");
+  }
+}
+
+air_status air_sweep_maxlog(air_ctx* ctx, const air_const* c, const uint32_t* tx_dev, const void* Z_dev,
+                            int64_t N, const double* snr_db_host, int S, air_prec prec, double* stats_dev,
+                            void* llr_dev) {
+  if (ctx && (!tx_dev || !stats_dev)) return fail(ctx, AIR_E_INVAL, "tx_dev and stats_dev must not be null");
+  try {
+    return run(ctx, c, Z_dev, tx_dev, N, snr_db_host, S, 1, prec, stats_dev, llr_dev, false, true);
   } catch (...) {
     return fail(ctx, AIR_E_NOMEM, "host allocation failed");
   }

@@ -70,6 +70,7 @@ template <> struct Real<float> {
   static __device__ __forceinline__ float starve(int m) { return __builtin_ldexpf(1.0f, m - 126 + 20); }
   static __device__ __forceinline__ float ln2() { return 0.693147180559945309f; }
   static __device__ __forceinline__ float nan() { return __builtin_nanf(""); }
+  static __device__ __forceinline__ float inf() { return __builtin_inff(); }
   static __device__ __forceinline__ float sigma(const SnrTable& t, int s) { return t.sigmaf[s]; }
   static __device__ __forceinline__ float c(const SnrTable& t, int s) { return t.cf[s]; }
 };
@@ -82,6 +83,7 @@ template <> struct Real<double> {
   static __device__ __forceinline__ double starve(int m) { return __builtin_ldexp(1.0, m - 1022 + 60); }
   static __device__ __forceinline__ double ln2() { return 0.6931471805599453094; }
   static __device__ __forceinline__ double nan() { return __builtin_nan(""); }
+  static __device__ __forceinline__ double inf() { return __builtin_inf(); }
   static __device__ __forceinline__ double sigma(const SnrTable& t, int s) { return t.sigma[s]; }
   static __device__ __forceinline__ double c(const SnrTable& t, int s) { return t.c[s]; }
 };

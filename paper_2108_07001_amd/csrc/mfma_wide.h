@@ -22,16 +22,26 @@
 
 namespace air {
 
-// Running sums of one lane over the point tiles, with LV tile levels.
-template <int NE, int LV>
+// How the per-point values of a sample are combined: sums of the terms
+// 2^a_j (exact demapping), or maxima of the exponents a_j (max-log).
+template <bool ML>
+__device__ __forceinline__ float cmb(float x, float y) {
+  if constexpr (ML) return __builtin_fmaxf(x, y);
+  else return x + y;
+}
+
+// Running sums (maxima for ML) of one lane over the point tiles, with LV
+// tile levels.
+template <int NE, int LV, bool ML = false>
 struct WideSums {
   float R[NE];
   float g0[LV > 0 ? LV : 1], g1[LV > 0 ? LV : 1], gn[LV > 0 ? LV : 1];
   float tot;
   __device__ __forceinline__ void init() {
+    const float z = ML ? -__builtin_inff() : 0.f;
 #pragma unroll
-    for (int l = 0; l < LV; ++l) { g0[l] = 0.f; g1[l] = 0.f; gn[l] = 0.f; }
-    tot = 0.f;
+    for (int l = 0; l < LV; ++l) { g0[l] = z; g1[l] = z; gn[l] = z; }
+    tot = z;
   }
   __device__ __forceinline__ void add(float (&ev)[NE], int t, int ntb) {
     if (t == 0) {
@@ -39,21 +49,21 @@ struct WideSums {
       for (int e = 0; e < NE; ++e) R[e] = ev[e];
     } else {
 #pragma unroll
-      for (int e = 0; e < NE; ++e) R[e] += ev[e];
+      for (int e = 0; e < NE; ++e) R[e] = cmb<ML>(R[e], ev[e]);
     }
 #pragma unroll
     for (int w2 = NE / 2; w2 >= 1; w2 >>= 1)
 #pragma unroll
-      for (int e = 0; e < w2; ++e) ev[e] = ev[2 * e] + ev[2 * e + 1];
+      for (int e = 0; e < w2; ++e) ev[e] = cmb<ML>(ev[2 * e], ev[2 * e + 1]);
     float carry = ev[0];
     bool placed = false;
 #pragma unroll
     for (int l = 0; l < LV; ++l) {
       if (!placed && l < ntb) {
         if ((t >> l) & 1) {
-          g0[l] += gn[l];
-          g1[l] += carry;
-          carry = gn[l] + carry;
+          g0[l] = cmb<ML>(g0[l], gn[l]);
+          g1[l] = cmb<ML>(g1[l], carry);
+          carry = cmb<ML>(gn[l], carry);
         } else {
           gn[l] = carry;
           placed = true;
@@ -219,7 +229,46 @@ struct WideSample {
 // point loop are then static), 0 for any M >= 32 taken at run time. The t2
 // list and partial-sum layouts are those of demap_mfma, so the second-tier
 // kernel is shared.
-template <int D, bool BF, bool TBL, int MB>
+// Max-log bit sides of one sample computed directly in FP32 (the matrix-core
+// operands of a sample out of the operand range): side[2k + b] = the largest
+// a_j = -c |y - x_j|^2 over the labels j with bit k equal to b.
+template <int D>
+__device__ __forceinline__ void maxlog_direct(const float (&y)[D], const float* __restrict__ xl, int M,
+                                              int m, float c, float (&side)[2 * kMaxBits]) {
+#pragma unroll
+  for (int i = 0; i < 2 * kMaxBits; ++i) side[i] = -__builtin_inff();
+  for (int j = 0; j < M; ++j) {
+    float d2 = 0.0f;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const float df = y[d] - xl[j * D + d];
+      d2 = __builtin_fmaf(df, df, d2);
+    }
+    const float aj = -c * d2;
+#pragma unroll
+    for (int k = 0; k < kMaxBits; ++k)
+      if (k < m) {
+        const bool b = (j >> k) & 1;
+        side[2 * k] = b ? side[2 * k] : __builtin_fmaxf(side[2 * k], aj);
+        side[2 * k + 1] = b ? __builtin_fmaxf(side[2 * k + 1], aj) : side[2 * k + 1];
+      }
+  }
+}
+
+// log2(1 + 2^x) in FP32 without overflow.
+__device__ __forceinline__ float softplus2(float x) {
+  const float ax = __builtin_fabsf(x);
+  return __builtin_fmaxf(x, 0.0f) + Real<float>::log2(1.0f + Real<float>::exp2(-ax));
+}
+
+// ML: the max-log form. Each bit side keeps the largest exponent instead of
+// the sum of the terms; the LLR is ln 2 times the difference of the two
+// sides' maxima, the GMI term is the BMD rate of those LLRs taken as exact,
+// sum_k log2(1 + 2^(-(1 - 2 b_k) L_k / ln 2)); the transmitted point's own
+// term, the logarithms of the sums and the second tier are not needed (no
+// sum can starve). Samples whose operands leave the operand range are done
+// by maxlog_direct.
+template <int D, bool BF, bool TBL, int MB, bool ML = false>
 __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(const DemapArgs a,
                                                     const typename MfmaOp<BF>::vec* __restrict__ rec,
                                                     const float* __restrict__ xl) {
@@ -292,7 +341,7 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
       // the transmitted points' own terms: diagonals of the products whose A
       // rows are the groups' transmitted points
       float arg_t = 0.f;
-      if (a.tx) {
+      if (!ML && a.tx) {
         V At[NK];
         const V* ra = tb.rec + ((int64_t)smA.tq * NK) * 2 + h;
 #pragma unroll
@@ -307,7 +356,7 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
         arg_t = hj ? hi : lo;
       }
 
-      WideSums<NE, LV> sA, sB;
+      WideSums<NE, LV, ML> sA, sB;
       sA.init();
       sB.init();
       {
@@ -325,10 +374,10 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
           }
           float ev[NE];
 #pragma unroll
-          for (int e = 0; e < NE; ++e) ev[e] = Real<float>::exp2(accA[e]);
+          for (int e = 0; e < NE; ++e) ev[e] = ML ? accA[e] : Real<float>::exp2(accA[e]);
           sA.add(ev, t, ntb);
 #pragma unroll
-          for (int e = 0; e < NE; ++e) ev[e] = Real<float>::exp2(accB[e]);
+          for (int e = 0; e < NE; ++e) ev[e] = ML ? accB[e] : Real<float>::exp2(accB[e]);
           sB.add(ev, t, ntb);
         }
       }
@@ -350,24 +399,24 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
       {
         float t0, t1;
         own_halves(sA.tot, sB.tot, t0, t1);
-        total = t0 + t1;
+        total = cmb<ML>(t0, t1);
       }
 #pragma unroll
       for (int l = 0; l < LV; ++l)
         if (l < ntb) {
           float x0, x1;
           own_halves(sA.g0[l], sB.g0[l], x0, x1);
-          side[2 * (5 + l)] = x0 + x1;
+          side[2 * (5 + l)] = cmb<ML>(x0, x1);
           own_halves(sA.g1[l], sB.g1[l], x0, x1);
-          side[2 * (5 + l) + 1] = x0 + x1;
+          side[2 * (5 + l) + 1] = cmb<ML>(x0, x1);
         }
       {
         // label bit 2 is the row half
         float c0 = r0[0], c1 = r1[0];
 #pragma unroll
         for (int e = 1; e < NE; ++e) {
-          c0 += r0[e];
-          c1 += r1[e];
+          c0 = cmb<ML>(c0, r0[e]);
+          c1 = cmb<ML>(c1, r1[e]);
         }
         side[4] = c0;
         side[5] = c1;
@@ -376,7 +425,7 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
         // label bits 0, 1, 3 (, 4) are the element bits 0, 1, 2 (, 3)
         float cur[NE];
 #pragma unroll
-        for (int e = 0; e < NE; ++e) cur[e] = r0[e] + r1[e];
+        for (int e = 0; e < NE; ++e) cur[e] = cmb<ML>(r0[e], r1[e]);
 #pragma unroll
         for (int eb = 0; eb < NEB; ++eb) {
           const int half = NE >> (eb + 1);
@@ -384,12 +433,12 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
 #pragma unroll
           for (int i = 1; i < NE / 2; ++i)
             if (i < half) {
-              a0 += cur[2 * i];
-              a1 += cur[2 * i + 1];
+              a0 = cmb<ML>(a0, cur[2 * i]);
+              a1 = cmb<ML>(a1, cur[2 * i + 1]);
             }
 #pragma unroll
           for (int i = 0; i < NE / 2; ++i)
-            if (i < half) cur[i] = cur[2 * i] + cur[2 * i + 1];
+            if (i < half) cur[i] = cmb<ML>(cur[2 * i], cur[2 * i + 1]);
           const int k = eb < 2 ? eb : eb + 1;
           side[2 * k] = a0;
           side[2 * k + 1] = a1;
@@ -397,6 +446,35 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
       }
 
       float* lout = (llr && valid) ? llr + (int64_t)s * a.llr_stride_s + n * m : nullptr;
+      if constexpr (ML) {
+        (void)total;
+        (void)thr;
+        if (live && ovf) {
+          float yo[D];
+#pragma unroll
+          for (int d = 0; d < D; ++d) yo[d] = h ? smB.y[d] : smA.y[d];
+          maxlog_direct<D>(yo, tb.xl, a.M, m, sp.c, side);
+          ++nlisted;                       // counted as recomputed below
+        }
+        float v = 0.f;
+        if (live) {
+#pragma unroll
+          for (int k = 0; k < kMaxBits; ++k)
+            if (k < m) {
+              const float lam = side[2 * k] - side[2 * k + 1];
+              if (lout) lout[k] = Real<float>::ln2() * lam;
+              if (tl >= 0) v += softplus2(((tl >> k) & 1) ? lam : -lam);
+            }
+        } else if (valid && lout) {
+          for (int k = 0; k < m; ++k) lout[k] = Real<float>::nan();
+        }
+        if (live && tl >= 0) {
+          const double dv = (double)v;
+          av += dv;
+          avv = __builtin_fma(dv, dv, avv);
+        }
+        continue;
+      }
       bool starved = ovf || !(total >= thr);
 #pragma unroll
       for (int i = 0; i < 2 * kMaxBits; ++i)
@@ -443,7 +521,13 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
         avv = __builtin_fma(dv, dv, avv);
       }
     }
-    if (lane == 0) a.t2_count[(int64_t)s * wstride + wgid] = (unsigned int)nlisted;
+    if constexpr (ML) {
+      // nlisted counted this lane's directly computed samples
+      const double wd = wave_sum((double)nlisted);
+      if (lane == 0 && wd > 0.0) atomicAdd(a.recomputed, (unsigned long long)wd);
+    } else {
+      if (lane == 0) a.t2_count[(int64_t)s * wstride + wgid] = (unsigned int)nlisted;
+    }
     const double w0 = wave_sum(au), w1 = wave_sum(av);
     const double w2 = wave_sum(auu), w3 = wave_sum(avv);
     if (lane == 0) {
@@ -480,6 +564,27 @@ inline void launch_t2_gather(const DemapArgs& a, int grid, hipStream_t st) {
 // One tier of the matrix-core path for one (D, operand type): part 0 is the
 // wide first tier in the variant the constellation size calls for, part 1 the
 // gather of its lists and the shared second tier.
+template <int D, bool BF, bool ML>
+void launch_first_tier(const DemapArgs& a, const typename MfmaOp<BF>::vec* r, const float* x, int grid,
+                       hipStream_t st) {
+  const size_t acc = sizeof(double) * 4 * a.S * 4;
+  const int64_t tbytes = table_bytes(a.M, D);
+  const bool tbl = tbytes <= 40 * 1024;
+  // the exact-size forms hold their tables in LDS (at most 12.5 KB for M = 64)
+  if (a.M == 16)
+    hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 4, ML>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
+  else if (a.M == 32)
+    hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 5, ML>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
+  else if (a.M == 64)
+    hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 6, ML>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
+  else if (tbl)
+    hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 0, ML>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
+  else
+    hipLaunchKernelGGL((demap_mfma_w<D, BF, false, 0, ML>), dim3(grid), dim3(256), acc, st, a, r, x);
+}
+
+// part 0: the exact first tier; 1: the gather and second tier; 2: the
+// max-log form (one kernel, no second tier).
 template <int D, bool BF>
 hipError_t launch_mfma_wide_td(const DemapArgs& a, const void* rec, int grid, hipStream_t st, int part) {
   const size_t acc = sizeof(double) * 4 * a.S * 4;
@@ -488,18 +593,9 @@ hipError_t launch_mfma_wide_td(const DemapArgs& a, const void* rec, int grid, hi
   typedef typename MfmaOp<BF>::vec V;
   const V* r = static_cast<const V*>(rec);
   const float* x = static_cast<const float*>(a.xl);
-  if (part == 0) {
-    // the exact-size forms hold their tables in LDS (at most 12.5 KB for M = 64)
-    if (a.M == 16)
-      hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 4>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
-    else if (a.M == 32)
-      hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 5>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
-    else if (a.M == 64)
-      hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 6>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
-    else if (tbl)
-      hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 0>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
-    else
-      hipLaunchKernelGGL((demap_mfma_w<D, BF, false, 0>), dim3(grid), dim3(256), acc, st, a, r, x);
+  if (part == 0 || part == 2) {
+    if (part == 0) launch_first_tier<D, BF, false>(a, r, x, grid, st);
+    else launch_first_tier<D, BF, true>(a, r, x, grid, st);
     return hipGetLastError();
   }
   launch_t2_gather(a, grid, st);

@@ -13,6 +13,11 @@
 //    which hands the totals of the two children of every completed node to
 //    the two sides of that level's label bit.
 // Every sum over a sample's points is then formed once, in a fixed order.
+//
+// ML: the max-log form with the same structure, maxima of the exponents in
+// place of sums of the terms; LLR = ln 2 (max side 0 - max side 1), the GMI
+// term is the BMD rate of those LLRs taken as exact; no sum can starve, so
+// the exact path is never needed.
 #pragma once
 #include "device_common.h"
 
@@ -38,7 +43,30 @@ __device__ __forceinline__ T tree_sum(const T (&e)[N]) {
   return buf[0];
 }
 
-template <typename T, int D, int G>
+template <bool ML, typename T>
+__device__ __forceinline__ T vcmb(T x, T y) {
+  if constexpr (ML) return x > y ? x : y;
+  else return x + y;
+}
+
+template <bool ML, typename T, int N>
+__device__ __forceinline__ T tree_cmb(const T (&e)[N]) {
+  if constexpr (!ML) {
+    return tree_sum<T, N>(e);
+  } else {
+    T buf[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) buf[i] = e[i];
+#pragma unroll
+    for (int w = N / 2; w >= 1; w >>= 1) {
+#pragma unroll
+      for (int i = 0; i < w; ++i) buf[i] = vcmb<true>(buf[2 * i], buf[2 * i + 1]);
+    }
+    return buf[0];
+  }
+}
+
+template <typename T, int D, int G, bool ML = false>
 __global__ __launch_bounds__(kBlock) void demap_vec(const DemapArgs a, const T* __restrict__ xl) {
   constexpr int LG = Log2G<G>::v;
   constexpr int NL = kMaxBits - LG;
@@ -80,33 +108,36 @@ __global__ __launch_bounds__(kBlock) void demap_vec(const DemapArgs a, const T* 
         T y[D];
         load_point<T, D>(a, n, tl, Real<T>::sigma(a.snr, s), y);
 
+        const T z0 = ML ? -Real<T>::inf() : T(0);
         T R[G];
         T hi0[NL], hi1[NL], node[NL];
 #pragma unroll
-        for (int l = 0; l < NL; ++l) { hi0[l] = 0; hi1[l] = 0; node[l] = 0; }
-        T total = 0;
+        for (int l = 0; l < NL; ++l) { hi0[l] = z0; hi1[l] = z0; node[l] = z0; }
+        T total = z0;
         for (int g = 0; g < NG; ++g) {
           const T* __restrict__ xg = xl + (int64_t)g * (G * D);
           T e[G];
 #pragma unroll
-          for (int i = 0; i < G; ++i)
-            e[i] = Real<T>::exp2(Real<T>::fma(-c, sqdist<T, D>(y, xg + i * D), K));
+          for (int i = 0; i < G; ++i) {
+            const T ai = Real<T>::fma(-c, sqdist<T, D>(y, xg + i * D), K);
+            e[i] = ML ? ai : Real<T>::exp2(ai);
+          }
           if (g == 0) {
 #pragma unroll
             for (int i = 0; i < G; ++i) R[i] = e[i];
           } else {
 #pragma unroll
-            for (int i = 0; i < G; ++i) R[i] += e[i];
+            for (int i = 0; i < G; ++i) R[i] = vcmb<ML>(R[i], e[i]);
           }
-          T carry = tree_sum<T, G>(e);
+          T carry = tree_cmb<ML, T, G>(e);
           bool placed = false;
 #pragma unroll
           for (int l = 0; l < NL; ++l) {
             if (!placed && l < ngb) {
               if ((g >> l) & 1) {
-                hi0[l] += node[l];
-                hi1[l] += carry;
-                carry = node[l] + carry;
+                hi0[l] = vcmb<ML>(hi0[l], node[l]);
+                hi1[l] = vcmb<ML>(hi1[l], carry);
+                carry = vcmb<ML>(node[l], carry);
               } else {
                 node[l] = carry;
                 placed = true;
@@ -121,11 +152,11 @@ __global__ __launch_bounds__(kBlock) void demap_vec(const DemapArgs a, const T* 
         for (int i = 0; i < 2 * kMaxBits; ++i) side[i] = 0;
 #pragma unroll
         for (int k = 0; k < LG; ++k) {
-          T s0 = 0, s1 = 0;
+          T s0 = z0, s1 = z0;
 #pragma unroll
           for (int i = 0; i < G; ++i) {
-            if ((i >> k) & 1) s1 += R[i];
-            else s0 += R[i];
+            if ((i >> k) & 1) s1 = vcmb<ML>(s1, R[i]);
+            else s0 = vcmb<ML>(s0, R[i]);
           }
           side[2 * k] = s0;
           side[2 * k + 1] = s1;
@@ -137,13 +168,30 @@ __global__ __launch_bounds__(kBlock) void demap_vec(const DemapArgs a, const T* 
             side[2 * (LG + l) + 1] = hi1[l];
           }
         }
-        T arg_t = 0;
-        if (tl >= 0) arg_t = Real<T>::fma(-c, sqdist<T, D>(y, xl + (int64_t)tl * D), K);
-        T u = 0, v = 0;
-        slow_items += finish_item<T, D>(exact_args<T>(a, s), n, tl, total, side, arg_t, lout, u, v) ? 1u : 0u;
-        if (tl >= 0) {
-          su = (double)u;
-          sv = (double)v;
+        if constexpr (ML) {
+          (void)total;
+          T v = 0;
+#pragma unroll
+          for (int k = 0; k < kMaxBits; ++k)
+            if (k < m) {
+              const T lam = side[2 * k] - side[2 * k + 1];
+              if (lout) lout[k] = Real<T>::ln2() * lam;
+              if (tl >= 0) {
+                const T x = ((tl >> k) & 1) ? lam : -lam;      // log2(1 + 2^x)
+                const T ax = x < T(0) ? -x : x;
+                v += (x > T(0) ? x : T(0)) + Real<T>::log2(T(1) + Real<T>::exp2(-ax));
+              }
+            }
+          if (tl >= 0) sv = (double)v;
+        } else {
+          T arg_t = 0;
+          if (tl >= 0) arg_t = Real<T>::fma(-c, sqdist<T, D>(y, xl + (int64_t)tl * D), K);
+          T u = 0, v = 0;
+          slow_items += finish_item<T, D>(exact_args<T>(a, s), n, tl, total, side, arg_t, lout, u, v) ? 1u : 0u;
+          if (tl >= 0) {
+            su = (double)u;
+            sv = (double)v;
+          }
         }
       } else if (lout) {
         for (int k = 0; k < m; ++k) lout[k] = Real<T>::nan();
@@ -174,20 +222,25 @@ __global__ __launch_bounds__(kBlock) void demap_vec(const DemapArgs a, const T* 
 }
 
 template <typename T, int D, int G>
-hipError_t launch_vec_one(const DemapArgs& a, int grid, hipStream_t st) {
+hipError_t launch_vec_one(const DemapArgs& a, int grid, hipStream_t st, bool ml) {
   const size_t shmem = sizeof(double) * (kBlock / 64) * a.S * 4;
-  hipLaunchKernelGGL((demap_vec<T, D, G>), dim3(grid), dim3(kBlock), shmem, st, a,
-                     static_cast<const T*>(a.xl));
+  if (ml)
+    hipLaunchKernelGGL((demap_vec<T, D, G, true>), dim3(grid), dim3(kBlock), shmem, st, a,
+                       static_cast<const T*>(a.xl));
+  else
+    hipLaunchKernelGGL((demap_vec<T, D, G, false>), dim3(grid), dim3(kBlock), shmem, st, a,
+                       static_cast<const T*>(a.xl));
   return hipGetLastError();
 }
 
+// ml: the max-log form.
 template <typename T, int D>
-hipError_t launch_vec_td(const DemapArgs& a, int grid, hipStream_t st) {
+hipError_t launch_vec_td(const DemapArgs& a, int grid, hipStream_t st, bool ml) {
   switch (a.M >= 16 ? 16 : a.M) {
-    case 2: return launch_vec_one<T, D, 2>(a, grid, st);
-    case 4: return launch_vec_one<T, D, 4>(a, grid, st);
-    case 8: return launch_vec_one<T, D, 8>(a, grid, st);
-    default: return launch_vec_one<T, D, 16>(a, grid, st);
+    case 2: return launch_vec_one<T, D, 2>(a, grid, st, ml);
+    case 4: return launch_vec_one<T, D, 4>(a, grid, st, ml);
+    case 8: return launch_vec_one<T, D, 8>(a, grid, st, ml);
+    default: return launch_vec_one<T, D, 16>(a, grid, st, ml);
   }
 }
 

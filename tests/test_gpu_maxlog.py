@@ -1,0 +1,116 @@
+"""GPU max-log demapping (air_llr_maxlog, air_gmi_maxlog, air_sweep_maxlog)
+against the oracle's max-log form on the same seeded inputs."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2108_07001_amd import air, inputs
+from tests.helpers import MI_TOL, assert_llr, to_dev, tx_dev
+
+pytestmark = pytest.mark.gpu
+
+LLR_BAR = {"fp64": 1e-11, "fp32": 1e-3, "fp16x3": 1e-3, "bf16x3": 1e-2}
+GMI_BAR = {"fp64": 1e-11, "fp32": MI_TOL, "fp16x3": MI_TOL, "bf16x3": MI_TOL}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = air.Context(0)
+    yield c
+    c.close()
+
+
+def _check(st, L, ref, prec):
+    st = st.cpu().numpy()
+    assert math.isnan(st[0]) and math.isnan(st[2])
+    assert abs(st[1] - ref["stats"][1]) <= GMI_BAR[prec], (st[1], ref["stats"][1])
+    assert st[3] == pytest.approx(ref["stats"][3], rel=1e-2, abs=1e-6)
+    assert_llr(L.cpu().numpy(), ref["llr"], rel=LLR_BAR[prec])
+
+
+@pytest.mark.parametrize("name,N,prec", [("psk8x8", 20_000, "fp16x3"), ("psk8x8", 5001, "fp32"),
+                                         ("psk8x8", 5001, "bf16x3"), ("gauss8d2048", 3000, "fp16x3"),
+                                         ("gauss12d4096", 1500, "fp16x3"), ("pmqpsk", 4000, "fp64"),
+                                         ("qam16", 7777, "fp16x3"), ("qam4", 3333, "fp32")])
+def test_gmi_maxlog_matches_oracle(ctx, name, N, prec):
+    w = inputs.make(name, N=N)
+    c = ctx.const(w.X, w.labels)
+    dt = np.float64 if prec == "fp64" else np.float32
+    for snr_db in (float(w.snr_db[0]), float(w.snr_db[-1]), 7.0):
+        Y = (w.X[w.tx] + math.sqrt(oracle.sigma2(w.X, snr_db)) * w.z.astype(np.float64)).astype(dt)
+        st, L = ctx.gmi_maxlog(c, to_dev(Y), tx_dev(w.tx), snr_db, prec, llr=True)
+        L2 = ctx.llr_maxlog(c, to_dev(Y), snr_db, prec)
+        ctx.sync()
+        ref = oracle.evaluate_maxlog(w.X, w.labels, Y.astype(np.float64), snr_db, tx=w.tx)
+        _check(st, L, ref, prec)
+        assert torch.equal(L, L2)
+    c.close()
+
+
+@pytest.mark.parametrize("M,D,N", [(2, 1, 1), (4, 3, 97), (16, 1, 257), (32, 5, 1000), (64, 16, 333),
+                                   (256, 2, 2049), (2048, 7, 500), (4096, 16, 100)])
+@pytest.mark.parametrize("prec", ["fp32", "fp16x3"])
+def test_maxlog_shapes(ctx, M, D, N, prec):
+    X, lab = inputs.random_constellation(M * 3 + D, M, D)
+    tx, z = inputs.random_block(M + 5 * D, M, N, D)
+    snr_db = 12.0
+    Y = (X[tx] + math.sqrt(oracle.sigma2(X, snr_db)) * z.astype(np.float64)).astype(np.float32)
+    c = ctx.const(X, lab)
+    st, L = ctx.gmi_maxlog(c, to_dev(Y), tx_dev(tx), snr_db, prec, llr=True)
+    ctx.sync()
+    ref = oracle.evaluate_maxlog(X, lab, Y.astype(np.float64), snr_db, tx=tx)
+    if N == 1:
+        assert abs(st.cpu().numpy()[1] - ref["stats"][1]) <= MI_TOL
+        assert_llr(L.cpu().numpy(), ref["llr"])
+    else:
+        _check(st, L, ref, prec)
+    c.close()
+
+
+@pytest.mark.parametrize("prec", ["fp16x3", "fp32"])
+def test_sweep_maxlog_matches_oracle(ctx, prec):
+    w = inputs.make("psk8x8", N=20_000)
+    c = ctx.const(w.X, w.labels)
+    st, L = ctx.sweep_maxlog(c, tx_dev(w.tx), to_dev(w.z, torch.float32), w.snr_db, prec, llr=True)
+    st2, _ = ctx.sweep_maxlog(c, tx_dev(w.tx), to_dev(w.z, torch.float32), w.snr_db, prec)
+    ctx.sync()
+    ref = oracle.sweep_maxlog(w.X, w.labels, w.tx, w.z, w.snr_db)
+    st = st.cpu().numpy()
+    assert np.isnan(st[:, 0]).all()
+    assert np.max(np.abs(st[:, 1] - ref["stats"][:, 1])) <= MI_TOL
+    assert_llr(L.cpu().numpy(), ref["llr"])
+    np.testing.assert_array_equal(st, st2.cpu().numpy())         # deterministic (NaN MI too)
+    c.close()
+
+
+def test_maxlog_operands_out_of_range_fall_back(ctx):
+    """At 70 dB the metric scale leaves the half-precision operand range: every
+    sample is demapped by the direct FP32 form, and still matches."""
+    w = inputs.make("psk8x8", N=3000)
+    c = ctx.const(w.X, w.labels)
+    snr_db = 70.0
+    Y = (w.X[w.tx] + math.sqrt(oracle.sigma2(w.X, snr_db)) * w.z.astype(np.float64)).astype(np.float32)
+    st, L = ctx.gmi_maxlog(c, to_dev(Y), tx_dev(w.tx), snr_db, "fp16x3", llr=True)
+    ctx.sync()
+    assert ctx.last_recomputed() == 3000
+    ref = oracle.evaluate_maxlog(w.X, w.labels, Y.astype(np.float64), snr_db, tx=w.tx)
+    assert abs(st.cpu().numpy()[1] - ref["stats"][1]) <= MI_TOL
+    assert_llr(L.cpu().numpy(), ref["llr"])
+    c.close()
+
+
+def test_maxlog_invalid_tx(ctx):
+    X, lab = inputs.random_constellation(77, 64, 4)
+    tx, z = inputs.random_block(78, 64, 500, 4)
+    bad = tx.astype(np.int64).copy()
+    bad[17] = 64
+    c = ctx.const(X, lab)
+    st, _ = ctx.gmi_maxlog(c, to_dev(z.astype(np.float32)), tx_dev(bad), 5.0, "fp16x3")
+    with pytest.raises(air.AirError) as e:
+        ctx.sync()
+    assert e.value.status == air.AIR_E_RANGE
+    assert np.isnan(st.cpu().numpy()).all()
+    c.close()
