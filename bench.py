@@ -28,21 +28,63 @@ TRANS_PEAK = 256 * 32 * 2.4e9
 PROFILES = os.path.join(ROOT, "profiles")
 
 
+# Sources of the matrix-core first tier and of its launch (grid, arguments):
+# stored counter data describes the kernel only while these are unchanged.
+FIRST_TIER_SOURCES = ("device_common.h", "mfma_kernels.h", "mfma_wide.h", "mfma_inst_f16_0.hip",
+                      "mfma_inst_bf16_0.hip", "vec_kernels.h", "vec_inst_f32_0.hip", "air_host.hip",
+                      "host_state.h")
+
+
 def source_hash() -> str:
-    """Digest of the HIP sources' code (comments and blank lines dropped), to
-    tell whether stored counter data still describes the kernels built."""
-    import glob
+    """Digest of the first tier's sources (comments and blank lines dropped),
+    to tell whether stored counter data still describes the kernel built."""
     import hashlib
     import re
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2108_07001_amd", "csrc", "*"))):
-        if f.endswith((".h", ".hip")):
-            h.update(os.path.basename(f).encode())
-            for line in open(f).read().splitlines():
-                code = re.sub(r"//.*$", "", line).rstrip()
-                if code:
-                    h.update(code.encode() + b"\n")
+    for name in FIRST_TIER_SOURCES:
+        h.update(name.encode())
+        for line in open(os.path.join(ROOT, "paper_2108_07001_amd", "csrc", name)).read().splitlines():
+            code = re.sub(r"//.*$", "", line).rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
+
+
+def traffic_from(out_dir: str, config: str, prec: str, kernel: str, commands: list) -> dict:
+    """HBM bytes per launch of `kernel` from rocprofv3 --pmc runs in out_dir:
+    f/ (FETCH_SIZE) and w/ (WRITE_SIZE) of the benchmark, cf/ and cw/ of the
+    1 GiB copy probe; each counter scaled by what it reads for the copy."""
+    import csv
+    import glob
+
+    def rows(sub):
+        f = glob.glob(os.path.join(out_dir, sub, "**", "*counter_collection.csv"), recursive=True)
+        if not f:
+            raise SystemExit(f"no counter_collection.csv under {out_dir}/{sub}")
+        return list(csv.DictReader(open(f[0])))
+
+    def per_dispatch(rs, pred):
+        vals = {}
+        for r in rs:
+            if pred(r["Kernel_Name"]):
+                vals[r["Dispatch_Id"]] = vals.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+        if not vals:
+            raise SystemExit("kernel not found in the counter data")
+        return sum(vals.values()) / len(vals), len(vals)
+
+    fk, nf = per_dispatch(rows("f"), lambda n: kernel in n)
+    wk, nw = per_dispatch(rows("w"), lambda n: kernel in n)
+    cf, _ = per_dispatch(rows("cf"), lambda n: "copyBuffer" in n)
+    cw, _ = per_dispatch(rows("cw"), lambda n: "copyBuffer" in n)
+    gib = float(1 << 30)
+    ff, wf = gib / (cf * 1024.0), gib / (cw * 1024.0)
+    fb, wb = fk * 1024.0 * ff, wk * 1024.0 * wf
+    return {"kernel": kernel, "workload": config, "prec": prec, "dispatches": [nf, nw],
+            "fetch_size_kib_per_dispatch": fk, "write_size_kib_per_dispatch": wk,
+            "copy_probe": {"bytes": int(gib), "fetch_size_kib": cf, "write_size_kib": cw,
+                           "fetch_factor": ff, "write_factor": wf},
+            "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb,
+            "source_hash": source_hash(), "commands": commands}
 
 
 def stored_traffic(workload: str, prec: str):
@@ -56,8 +98,45 @@ def stored_traffic(workload: str, prec: str):
     return d["bytes_per_launch"] if d.get("source_hash") == source_hash() else None
 
 
+# Name of the exact first tier as the profiler prints it (template arguments
+# D, bfloat16 operands, tables in LDS, exact-size form log2 M or 0, max-log).
+FIRST_TIER_KERNEL = "demap_mfma_w<{D}, {BF}, true, {MB}, false>"
+
+
+def inputs_config(name: str) -> dict:
+    from paper_2108_07001_amd import inputs
+    return inputs.CONFIGS[name]
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def maxlog(ctx, c, w, tx, prec: str, steps: int) -> dict:
+    """The same sweep in the max-log form (air_sweep_maxlog): LLRs from the
+    largest term of each bit side, GMI of those LLRs; no symbol-wise MI."""
+    import torch
+    dev = ctx.torch_device
+    S, N, m = len(w.snr_db), w.N, w.m
+    zt = torch.from_numpy(w.z).to(dev)
+    stats = torch.empty((S, 4), dtype=torch.float64, device=dev)
+    L = torch.empty((S, N, m), dtype=torch.float32, device=dev)
+    ctx.sweep_maxlog(c, tx, zt, w.snr_db, prec=prec, stats_out=stats, llr_out=L)
+    ctx.sync()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.sweep_maxlog(c, tx, zt, w.snr_db, prec=prec, stats_out=stats, llr_out=L)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    kms, launches = ctx.kernel_time()
+    ctx.set_timing(False)
+    ctx.sync()
+    st = stats.cpu().numpy()
+    return {"prec": prec, "ms_per_step": ms, "kernel_ms": kms / max(launches, 1),
+            "sample_points_per_s": float(N) * S * w.M / (ms * 1e-3),
+            "gmi": [float(x) for x in st[:, 1]]}
 
 
 def hard_decisions(ctx, c, w, tx, steps: int) -> dict:
@@ -230,10 +309,31 @@ def main():
                     help="jobs of the Poisson serving mix to replay (0: skip; full mix: 20000)")
     ap.add_argument("--stream-buffers", type=int, default=12,
                     help="2^20-symbol M-QAM buffers per format streamed from host memory (0: skip)")
+    ap.add_argument("--traffic-from", default=None,
+                    help="write profiles/traffic_<config>_<prec>.json from rocprofv3 --pmc "
+                         "FETCH_SIZE / WRITE_SIZE runs of the benchmark (f/, w/) and of "
+                         "--copy-probe (cf/, cw/) under this directory, then exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device-to-device copy of 1 GiB (3 times), the "
                          "reference for scaling hardware byte counters")
     args = ap.parse_args()
+    if args.traffic_from:
+        prec = args.prec or "fp16x3"
+        w0 = inputs_config(args.config)
+        kern = FIRST_TIER_KERNEL.format(D=w0["D"], BF="true" if prec == "bf16x3" else "false",
+                                        MB={16: 4, 32: 5, 64: 6}.get(w0["M"], 0))
+        run = (f"python3 bench.py --config {args.config} --prec {prec} --no-cpu --no-fp32 --steps 5 "
+               f"--warmup 1 --serving-jobs 0 --stream-buffers 0")
+        cmds = [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/f -o f -- {run}",
+                f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/w -o w -- {run}",
+                "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/cf -o cf -- python3 bench.py --copy-probe",
+                "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/cw -o cw -- python3 bench.py --copy-probe",
+                f"python3 bench.py --config {args.config} --prec {prec} --traffic-from <out>"]
+        d = traffic_from(args.traffic_from, args.config, prec, kern, cmds)
+        p = os.path.join(PROFILES, f"traffic_{args.config}_{prec}.json")
+        json.dump(d, open(p, "w"), indent=1)
+        print(json.dumps({"wrote": p, "bytes_per_launch": d["bytes_per_launch"]}))
+        return
     if args.copy_probe:
         import torch
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -342,6 +442,9 @@ def main():
                               "kernel_ms": f["kernel_ms"]}
         line["speedup_vs_fp32"] = f["ms"] / r["ms"]
 
+    if chosen in ("fp16x3", "bf16x3", "fp32"):
+        line["maxlog"] = maxlog(ctx, c, w, tx, chosen, args.steps)
+        line["maxlog"]["speedup_vs_exact"] = r["ms"] / line["maxlog"]["ms_per_step"]
     line["hard_decisions"] = hard_decisions(ctx, c, w, tx, max(3, args.steps // 4))
 
     if args.stream_buffers > 0:

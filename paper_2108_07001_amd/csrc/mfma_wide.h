@@ -102,15 +102,37 @@ struct WideOperand {
 #pragma unroll
     for (int k = 0; k < KP; ++k) F[k] = (E)0.0f;
     ovf = !(c < 60000.0f);
+    if constexpr (!BF) {
+      // half precision: split two dimensions at a time with the packed
+      // conversion (round to nearest even), which writes whole registers
+      typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+      typedef float f2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const float w = 2.0f * c * y[d];
-      ovf |= !(__builtin_fabsf(w) < 60000.0f);
-      E hi, lo;
-      split2<BF>(w, hi, lo);
-      F[d] = hi;
-      F[D + d] = hi;
-      F[2 * D + d] = lo;
+      for (int d = 0; d < D; d += 2) {
+        const float w0 = 2.0f * c * y[d];
+        const float w1 = d + 1 < D ? 2.0f * c * y[d + 1 < D ? d + 1 : d] : 0.0f;
+        ovf |= !(__builtin_fmaxf(__builtin_fabsf(w0), __builtin_fabsf(w1)) < 60000.0f);
+        const f2 w = {w0, w1};
+        const h2 hi = __builtin_convertvector(w, h2);
+        const h2 lo = __builtin_convertvector(w - __builtin_convertvector(hi, f2), h2);
+        F[d] = hi.x;
+        F[D + d] = hi.x;
+        F[2 * D + d] = lo.x;
+        if (d + 1 < D) {
+          F[d + 1] = hi.y;
+          F[D + d + 1] = hi.y;
+          F[2 * D + d + 1] = lo.y;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        E hi, lo;
+        split2<BF>(2.0f * c * y[d], hi, lo);
+        F[d] = hi;
+        F[D + d] = hi;
+        F[2 * D + d] = lo;
+      }
     }
     {
       E hi, lo;
@@ -213,11 +235,14 @@ struct WideSample {
     tl = has_t ? (inb ? lab : -2) : -1;
     live = valid && !bad;
     tq = tl >= 0 ? tl : 0;
+    // sweep: y = fma(sigma, z, x_t); a given block: y = fma(1, y, 0 * x) = y.
+    // Lanes that are not live keep finite values (the fetch is clamped to a
+    // real sample, the record read to label 0): they only feed their own
+    // column of each product, whose outputs are dropped.
+    const float ga = p.sweep ? p.sigma : 1.0f;
+    const float gx = p.sweep ? 1.0f : 0.0f;
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const float zi = live ? ri.z[d] : 0.0f;
-      y[d] = p.sweep ? __builtin_fmaf(p.sigma, zi, live ? xv[d] : 0.0f) : zi;
-    }
+    for (int d = 0; d < D; ++d) y[d] = __builtin_fmaf(ga, ri.z[d], xv[d] * gx);
   }
 };
 
@@ -313,17 +338,23 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
   const int64_t wgid = (int64_t)blockIdx.x * waves + wave;
   const bool hj = (j >> 2) & 1;           // lane half holding row j of a tile
 
+  // Per SNR point the waves take the pairs q0, q0 + wstride, ... with q0 =
+  // (wgid + s * rem) mod wstride, rem = npairs mod wstride: the waves that
+  // get one round more than the others change from one SNR point to the
+  // next, so over a sweep every wave does nearly the same number of rounds.
+  const int64_t rem = npairs % wstride;
   for (int s = 0; s < S; ++s) {
     double au = 0.0, av = 0.0, auu = 0.0, avv = 0.0;
     unsigned long long* slots = a.t2_list + ((int64_t)s * wstride + wgid) * a.t2_tpw;
     int nlisted = 0;
     const SampleParams sp = sample_params(a, s);
+    const int64_t q0 = (wgid + ((int64_t)s * rem) % wstride) % wstride;
     RawInput<D> curA, curB, nxtA, nxtB;
-    if (wgid < npairs) {
-      curA.fetch(sp, 2 * wgid, j);
-      curB.fetch(sp, 2 * wgid + 1, j);
+    if (q0 < npairs) {
+      curA.fetch(sp, 2 * q0, j);
+      curB.fetch(sp, 2 * q0 + 1, j);
     }
-    for (int64_t q = wgid; q < npairs; q += wstride) {
+    for (int64_t q = q0; q < npairs; q += wstride) {
       {
         const int64_t qn = q + wstride < npairs ? q + wstride : npairs - 1;
         nxtA.fetch(sp, 2 * qn, j);          // next round's inputs, ahead of use
@@ -475,10 +506,13 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
         }
         continue;
       }
-      bool starved = ovf || !(total >= thr);
+      // every sum is finite and >= 0 unless the operands left their range
+      // (ovf), so the smallest of them decides
+      float smin = total;
 #pragma unroll
       for (int i = 0; i < 2 * kMaxBits; ++i)
-        if (i < 2 * m) starved |= !(side[i] >= thr);
+        if (i < 2 * m) smin = __builtin_fminf(smin, side[i]);
+      const bool starved = ovf || !(smin >= thr);
       float u = 0.f, v = 0.f;
       if (live && !starved) {
         const float lam_tot = Real<float>::log2(total);
