@@ -339,16 +339,20 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
   const bool hj = (j >> 2) & 1;           // lane half holding row j of a tile
 
   // Per SNR point the waves take the pairs q0, q0 + wstride, ... with q0 =
-  // (wgid + s * rem) mod wstride, rem = npairs mod wstride: the waves that
-  // get one round more than the others change from one SNR point to the
-  // next, so over a sweep every wave does nearly the same number of rounds.
+  // (wgid + sh) mod wstride, sh = (s * rem mod wstride) rounded down to a
+  // multiple of 32, rem = npairs mod wstride: the waves that get one round
+  // more than the others change from one SNR point to the next, so over a
+  // sweep every wave does nearly the same number of rounds. Shifting by
+  // multiples of 32 waves (8 blocks) keeps each pair on the same XCD
+  // (blocks are dealt to the 8 XCDs in turn), whose L2 still holds its
+  // inputs from the previous SNR point.
   const int64_t rem = npairs % wstride;
   for (int s = 0; s < S; ++s) {
     double au = 0.0, av = 0.0, auu = 0.0, avv = 0.0;
     unsigned long long* slots = a.t2_list + ((int64_t)s * wstride + wgid) * a.t2_tpw;
     int nlisted = 0;
     const SampleParams sp = sample_params(a, s);
-    const int64_t q0 = (wgid + ((int64_t)s * rem) % wstride) % wstride;
+    const int64_t q0 = (wgid + ((((int64_t)s * rem) % wstride) & ~(int64_t)31)) % wstride;
     RawInput<D> curA, curB, nxtA, nxtB;
     if (q0 < npairs) {
       curA.fetch(sp, 2 * q0, j);
