@@ -31,7 +31,9 @@ __device__ __forceinline__ float cmb(float x, float y) {
 }
 
 // Running sums (maxima for ML) of one lane over the point tiles, with LV
-// tile levels.
+// tile levels. The two forms are written out separately: the sums' form is
+// kept exactly as the compiler handles it best (its level arrays stay in
+// registers in the run-time-M form).
 template <int NE, int LV, bool ML = false>
 struct WideSums {
   float R[NE];
@@ -44,33 +46,66 @@ struct WideSums {
     tot = z;
   }
   __device__ __forceinline__ void add(float (&ev)[NE], int t, int ntb) {
-    if (t == 0) {
+    if constexpr (ML) {
+      // (in the run-time-M form the compiler keeps g0 / g1 of this form in
+      // scratch; an order-free update of every level per tile, which avoids
+      // that, measured slower)
+      if (t == 0) {
 #pragma unroll
-      for (int e = 0; e < NE; ++e) R[e] = ev[e];
-    } else {
+        for (int e = 0; e < NE; ++e) R[e] = ev[e];
+      } else {
 #pragma unroll
-      for (int e = 0; e < NE; ++e) R[e] = cmb<ML>(R[e], ev[e]);
-    }
+        for (int e = 0; e < NE; ++e) R[e] = __builtin_fmaxf(R[e], ev[e]);
+      }
 #pragma unroll
-    for (int w2 = NE / 2; w2 >= 1; w2 >>= 1)
+      for (int w2 = NE / 2; w2 >= 1; w2 >>= 1)
 #pragma unroll
-      for (int e = 0; e < w2; ++e) ev[e] = cmb<ML>(ev[2 * e], ev[2 * e + 1]);
-    float carry = ev[0];
-    bool placed = false;
+        for (int e = 0; e < w2; ++e) ev[e] = __builtin_fmaxf(ev[2 * e], ev[2 * e + 1]);
+      float carry = ev[0];
+      bool placed = false;
 #pragma unroll
-    for (int l = 0; l < LV; ++l) {
-      if (!placed && l < ntb) {
-        if ((t >> l) & 1) {
-          g0[l] = cmb<ML>(g0[l], gn[l]);
-          g1[l] = cmb<ML>(g1[l], carry);
-          carry = cmb<ML>(gn[l], carry);
-        } else {
-          gn[l] = carry;
-          placed = true;
+      for (int l = 0; l < LV; ++l) {
+        if (!placed && l < ntb) {
+          if ((t >> l) & 1) {
+            g0[l] = __builtin_fmaxf(g0[l], gn[l]);
+            g1[l] = __builtin_fmaxf(g1[l], carry);
+            carry = __builtin_fmaxf(gn[l], carry);
+          } else {
+            gn[l] = carry;
+            placed = true;
+          }
         }
       }
+      if (!placed) tot = carry;
+    } else {
+      if (t == 0) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) R[e] = ev[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) R[e] += ev[e];
+      }
+#pragma unroll
+      for (int w2 = NE / 2; w2 >= 1; w2 >>= 1)
+#pragma unroll
+        for (int e = 0; e < w2; ++e) ev[e] = ev[2 * e] + ev[2 * e + 1];
+      float carry = ev[0];
+      bool placed = false;
+#pragma unroll
+      for (int l = 0; l < LV; ++l) {
+        if (!placed && l < ntb) {
+          if ((t >> l) & 1) {
+            g0[l] += gn[l];
+            g1[l] += carry;
+            carry = gn[l] + carry;
+          } else {
+            gn[l] = carry;
+            placed = true;
+          }
+        }
+      }
+      if (!placed) tot = carry;
     }
-    if (!placed) tot = carry;
   }
 };
 
