@@ -283,7 +283,9 @@ air_status air_pipe_push(air_pipe *p, const void *Y_host, int64_t N, double snr_
  * air_sync on the context (reports its errors). */
 air_status air_pipe_wait(air_pipe *p);
 
-/* Release a pipe (waits for its queued work). NULL is ignored. */
+/* Release a pipe. Waits for its queued work; the LLRs of buffers pushed since
+ * the last air_pipe_wait are then not delivered to pageable llr_host buffers
+ * (pinned ones receive them). NULL is ignored. */
 void air_pipe_destroy(air_pipe *p);
 
 /* ---------------------------------------------------------------------------
