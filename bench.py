@@ -24,7 +24,9 @@ sys.path.insert(0, ROOT)
 
 # Transcendental roof of MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock at half
 # rate for v_exp_f32 / v_log_f32 (32 per clock per CU), 2.4 GHz.
-TRANS_PEAK = 256 * 32 * 2.4e9
+CLOCK_HZ = 2.4e9
+SIMDS = 256 * 4                        # 256 CUs x 4 SIMDs
+TRANS_PEAK = 256 * 32 * CLOCK_HZ       # exp2/log2 per second (half rate)
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -85,6 +87,42 @@ def traffic_from(out_dir: str, config: str, prec: str, kernel: str, commands: li
                            "fetch_factor": ff, "write_factor": wf},
             "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb,
             "source_hash": source_hash(), "commands": commands}
+
+
+def counters_from(out_dir: str, kernel: str) -> dict:
+    """Per-dispatch averages of every counter of `kernel` in one rocprofv3
+    --pmc run under out_dir."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(out_dir, "**", "*counter_collection.csv"), recursive=True)
+    if not f:
+        raise SystemExit(f"no counter_collection.csv under {out_dir}")
+    acc = {}
+    for r in csv.DictReader(open(f[0])):
+        if kernel in r["Kernel_Name"]:
+            d = acc.setdefault(r["Counter_Name"], {})
+            d[r["Dispatch_Id"]] = d.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    if not acc:
+        raise SystemExit("kernel not found in the counter data")
+    return {k: sum(v.values()) / len(v) for k, v in acc.items()}
+
+
+def stored_issue(workload: str, prec: str, kernel_ms: float):
+    """VALU issue of the main kernel from the committed SQ counter summary:
+    instructions per launch and the fraction of the issue limit (one wave64
+    VALU instruction per SIMD every 4 cycles) they take at the measured launch
+    time; None when there is no summary or the sources changed since."""
+    p = os.path.join(PROFILES, f"sq_{workload}_{prec}.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("source_hash") != source_hash():
+        return None
+    cycles = kernel_ms * 1e-3 * CLOCK_HZ
+    return {"valu_insts_per_launch": d["SQ_INSTS_VALU"],
+            "insts_per_simd_cycle": d["SQ_INSTS_VALU"] / (SIMDS * cycles),
+            "frac_of_issue_limit": d["SQ_INSTS_VALU"] * 4.0 / (SIMDS * cycles),
+            "note": "exp2/log2 occupy the SIMD for two issue slots; they are counted once here"}
 
 
 def stored_traffic(workload: str, prec: str):
@@ -316,6 +354,9 @@ def main():
                     help="write profiles/traffic_<config>_<prec>.json from rocprofv3 --pmc "
                          "FETCH_SIZE / WRITE_SIZE runs of the benchmark (f/, w/) and of "
                          "--copy-probe (cf/, cw/) under this directory, then exit")
+    ap.add_argument("--sq-from", default=None,
+                    help="write profiles/sq_<config>_<prec>.json from a rocprofv3 --pmc run of "
+                         "SQ counters of the benchmark under this directory, then exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device-to-device copy of 1 GiB (3 times), the "
                          "reference for scaling hardware byte counters")
@@ -336,6 +377,22 @@ def main():
         p = os.path.join(PROFILES, f"traffic_{args.config}_{prec}.json")
         json.dump(d, open(p, "w"), indent=1)
         print(json.dumps({"wrote": p, "bytes_per_launch": d["bytes_per_launch"]}))
+        return
+    if args.sq_from:
+        prec = args.prec or "fp16x3"
+        w0 = inputs_config(args.config)
+        kern = FIRST_TIER_KERNEL.format(D=w0["D"], BF="true" if prec == "bf16x3" else "false",
+                                        MB={16: 4, 32: 5, 64: 6}.get(w0["M"], 0))
+        d = counters_from(args.sq_from, kern)
+        d.update(kernel=kern, workload=args.config, prec=prec, source_hash=source_hash(),
+                 commands=[f"rocprofv3 --pmc {' '.join(sorted(k for k in d if k.startswith('SQ_')))} "
+                           f"--output-format csv -d <out> -o sq -- python3 bench.py --config {args.config} "
+                           f"--prec {prec} --no-cpu --no-fp32 --steps 5 --warmup 1 --serving-jobs 0 "
+                           f"--stream-buffers 0",
+                           f"python3 bench.py --config {args.config} --prec {prec} --sq-from <out>"])
+        p = os.path.join(PROFILES, f"sq_{args.config}_{prec}.json")
+        json.dump(d, open(p, "w"), indent=1)
+        print(json.dumps({"wrote": p}))
         return
     if args.copy_probe:
         import torch
@@ -431,6 +488,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": TRANS_PEAK / 1e12,
                      "unit": "Ttranscendentals/s", "frac": achieved / TRANS_PEAK,
                      "traffic": stored_traffic(args.config, chosen),
+                     "valu_issue": stored_issue(args.config, chosen, r["kernel_ms"]),
                      "kernel": "first tier (demap_mfma_w)" if chosen in ("fp16x3", "bf16x3")
                                else "demap_vec",
                      "kernel_ms": r["kernel_ms"], "launches_per_step": r["launches"],
