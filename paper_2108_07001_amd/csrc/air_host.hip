@@ -105,11 +105,21 @@ __global__ __launch_bounds__(256) void finish_kernel(const double* __restrict__ 
   const int s = blockIdx.x;
   const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double t = 0.0;
+  // each lane's blocks (at most kMaxGrid / 64 = 16 per list) loaded at once,
+  // then added in block order
+  constexpr int kPer = kMaxGrid / 64;
   const double* p = partials + ((int64_t)s * 4 + q) * nblocks;
-  for (int b = lane; b < nblocks; b += 64) t += p[b];
+  double v[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) v[i] = lane + 64 * i < nblocks ? p[lane + 64 * i] : 0.0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) t += v[i];
   if (t2_partials) {
     const double* p2 = t2_partials + ((int64_t)s * 4 + q) * nblocks2;
-    for (int b = lane; b < nblocks2; b += 64) t += p2[b];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) v[i] = lane + 64 * i < nblocks2 ? p2[lane + 64 * i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) t += v[i];
   }
   t = wave_sum(t);
   if (lane == 0) sums[q] = t;

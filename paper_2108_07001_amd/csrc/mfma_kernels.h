@@ -546,14 +546,19 @@ __device__ __forceinline__ bool tier2_tile(const SampleTile<D, BF>& smp, const T
 static __global__ __launch_bounds__(256) void t2_scan(const unsigned int* __restrict__ counts, int W,
                                                unsigned int* __restrict__ loc,
                                                unsigned int* __restrict__ tot) {
+  constexpr int kPer = 16;                 // W <= 256 * kPer (kMaxGrid waves of 4)
   __shared__ unsigned int part[256];
   const int s = blockIdx.x;
   const unsigned int* c = counts + (int64_t)s * W;
   const int per = (W + 255) / 256;
   const int w0 = threadIdx.x * per;
-  const int w1 = w0 + per < W ? w0 + per : W;
+  // all of this thread's counts in flight at once, then summed in order
+  unsigned int cv[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) cv[i] = (i < per && w0 + i < W) ? c[w0 + i] : 0u;
   unsigned int sum = 0;
-  for (int w = w0; w < w1; ++w) sum += c[w];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) sum += cv[i];
   part[threadIdx.x] = sum;
   __syncthreads();
   for (int off = 1; off < 256; off <<= 1) {
@@ -563,10 +568,12 @@ static __global__ __launch_bounds__(256) void t2_scan(const unsigned int* __rest
     __syncthreads();
   }
   unsigned int run = part[threadIdx.x] - sum;
-  for (int w = w0; w < w1; ++w) {
-    loc[(int64_t)s * W + w] = run;
-    run += c[w];
-  }
+#pragma unroll
+  for (int i = 0; i < kPer; ++i)
+    if (i < per && w0 + i < W) {
+      loc[(int64_t)s * W + w0 + i] = run;
+      run += cv[i];
+    }
   if (threadIdx.x == 255) tot[s] = part[255];
 }
 
