@@ -466,9 +466,9 @@ class Pipe:
 
     def _host(self, x, shape, name):
         dt = np.float64 if self.prec == "fp64" else np.float32
+        tdt = torch.float64 if self.prec == "fp64" else torch.float32
         if isinstance(x, torch.Tensor):
-            if x.device.type != "cpu" or x.dtype != torch.from_numpy(np.zeros(1, dt)).dtype \
-                    or tuple(x.shape) != shape or not x.is_contiguous():
+            if x.device.type != "cpu" or x.dtype != tdt or tuple(x.shape) != shape or not x.is_contiguous():
                 raise AirError(AIR_E_INVAL, f"{name} must be a contiguous host {dt.__name__} tensor {shape}")
             return x.data_ptr()
         if not isinstance(x, np.ndarray) or x.dtype != dt or x.shape != shape or not x.flags.c_contiguous:

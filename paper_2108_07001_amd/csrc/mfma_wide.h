@@ -632,11 +632,8 @@ inline void launch_t2_gather(const DemapArgs& a, int grid, hipStream_t st) {
                      a.t2_loc, a.t2_tot, W, a.S, a.t2_tpw, a.t2_comp, a.t2_comp_s);
 }
 
-// Both tiers for one (D, operand type): the wide first tier in the variant
-// the constellation size calls for, then the shared second tier.
-// One tier of the matrix-core path for one (D, operand type): part 0 is the
-// wide first tier in the variant the constellation size calls for, part 1 the
-// gather of its lists and the shared second tier.
+// The wide first tier (exact or max-log) in the variant the constellation
+// size calls for.
 template <int D, bool BF, bool ML>
 void launch_first_tier(const DemapArgs& a, const typename MfmaOp<BF>::vec* r, const float* x, int grid,
                        hipStream_t st) {
@@ -656,8 +653,9 @@ void launch_first_tier(const DemapArgs& a, const typename MfmaOp<BF>::vec* r, co
     hipLaunchKernelGGL((demap_mfma_w<D, BF, false, 0, ML>), dim3(grid), dim3(256), acc, st, a, r, x);
 }
 
-// part 0: the exact first tier; 1: the gather and second tier; 2: the
-// max-log form (one kernel, no second tier).
+// One part of the matrix-core path for one (D, operand type). part 0: the
+// exact first tier; 1: the gather of its lists and the shared second tier;
+// 2: the max-log form (one kernel, no second tier).
 template <int D, bool BF>
 hipError_t launch_mfma_wide_td(const DemapArgs& a, const void* rec, int grid, hipStream_t st, int part) {
   const size_t acc = sizeof(double) * 4 * a.S * 4;
