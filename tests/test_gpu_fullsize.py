@@ -72,3 +72,24 @@ def test_large_sets_full_size_sampled(ctx, name, nsample):
     assert np.isfinite(st).all()
     _halves_consistent(ctx, c, w, st)
     c.close()
+
+
+def test_psk8x8_full_size_maxlog_and_hard_decisions(ctx):
+    """The max-log sweep and the hard-decision sweep at the full workload
+    size, against the oracle's forms on the whole workload."""
+    w = inputs.make("psk8x8")
+    c = ctx.const(w.X, w.labels)
+    txd, zd = tx_dev(w.tx), to_dev(w.z, torch.float32)
+    st, L = ctx.sweep_maxlog(c, txd, zd, w.snr_db, prec="fp16x3", llr=True)
+    counts, _ = ctx.hard_sweep(c, txd, zd, w.snr_db)
+    ctx.sync()
+    ref = oracle.sweep_maxlog(w.X, w.labels, w.tx, w.z, w.snr_db)
+    st = st.cpu().numpy()
+    assert np.isnan(st[:, 0]).all()
+    assert np.max(np.abs(st[:, 1] - ref["stats"][:, 1])) <= 1e-4
+    assert_llr(L.cpu().numpy(), ref["llr"])
+    del L
+    torch.cuda.empty_cache()
+    hd = oracle.hard_decisions_sweep(w.X, w.labels, w.tx, w.z.astype(np.float32), w.snr_db)
+    np.testing.assert_array_equal(counts.cpu().numpy().astype(np.uint64), hd["counts"])
+    c.close()
