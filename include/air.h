@@ -67,9 +67,11 @@ typedef enum {
  *              (three products per term) with FP32 accumulation; FP32 log-sum-exp.
  *  AIR_FP16X3  as AIR_BF16X3 with half-precision hi+lo splits.
  * Except AIR_FP64, Y / Z are float and LLRs float. Sums over samples are
- * always FP64. Every FP32-family result that is not representable within the
- * stated accuracy by the fast path (very large |LLR|, a received point far
- * from every constellation point) is recomputed exactly in FP32. */
+ * always FP64. A result the fast FP32 frame cannot hold to the stated
+ * accuracy (very large |LLR|, a received point far from every constellation
+ * point) is recomputed: by the matrix-core forms' second tier with every
+ * term in an FP64 frame, and beyond that (or in the vector forms) by an
+ * exact per-sample path relative to the nearest point. */
 typedef enum {
   AIR_FP64 = 0,
   AIR_FP32 = 1,
