@@ -235,13 +235,13 @@ void fill_snr(SnrTable& t, const air_const* c, const double* snr_db, int S, bool
 void free_t2(air_ctx* ctx) {
   (void)hipFree(ctx->t2_list);
   (void)hipFree(ctx->t2_count);
-  (void)hipFree(ctx->t2_comp);
-  (void)hipFree(ctx->t2_comp_s);
+  (void)hipFree(ctx->t2_nitem);
+  (void)hipFree(ctx->t2_items);
   (void)hipFree(ctx->t2_loc);
   ctx->t2_list = nullptr;
   ctx->t2_count = nullptr;
-  ctx->t2_comp = nullptr;
-  ctx->t2_comp_s = nullptr;
+  ctx->t2_nitem = nullptr;
+  ctx->t2_items = nullptr;
   ctx->t2_loc = nullptr;
   ctx->t2_slots = ctx->t2_counts = 0;
 }
@@ -252,8 +252,10 @@ air_status ensure_t2(air_ctx* ctx, int64_t slots, int64_t counts) {
   free_t2(ctx);
   hipError_t e = hipMalloc(&ctx->t2_list, sizeof(unsigned long long) * slots);
   if (e == hipSuccess) e = hipMalloc(&ctx->t2_count, sizeof(unsigned int) * counts);
-  if (e == hipSuccess) e = hipMalloc(&ctx->t2_comp, sizeof(unsigned long long) * slots);
-  if (e == hipSuccess) e = hipMalloc(&ctx->t2_comp_s, slots);
+  if (e == hipSuccess) e = hipMalloc(&ctx->t2_nitem, sizeof(unsigned int) * counts);
+  // every slot lists one 32-sample tile, so the dense list holds at most 32
+  // samples per slot (the padding of each SNR run to 32 fits in the same bound)
+  if (e == hipSuccess) e = hipMalloc(&ctx->t2_items, sizeof(uint32_t) * 32 * slots);
   if (e == hipSuccess) e = hipMalloc(&ctx->t2_loc, sizeof(unsigned int) * counts);
   if (e != hipSuccess) {
     free_t2(ctx);
@@ -319,7 +321,8 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
     const int64_t waves = (int64_t)grid * 4;
     const int64_t npairs = (ntiles + 1) / 2;
     const int64_t tpw = 2 * ((npairs + waves - 1) / waves);
-    if (ntiles >= ((int64_t)1 << 32)) return fail(ctx, AIR_E_UNSUPPORTED, "N too large for one call");
+    // tile indices and per-SNR sample counts of the second tier are 32-bit
+    if (N >= ((int64_t)1 << 32)) return fail(ctx, AIR_E_UNSUPPORTED, "N too large for one call");
     const int64_t sl = S < kMaxSnrPerLaunch ? S : kMaxSnrPerLaunch;
     const air_status st = ensure_t2(ctx, sl * waves * tpw, sl * waves);
     if (st != AIR_OK) return st;
@@ -327,8 +330,8 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
     a.t2_count = ctx->t2_count;
     a.t2_partials = ctx->t2_partials;
     a.t2_tpw = (int)tpw;
-    a.t2_comp = ctx->t2_comp;
-    a.t2_comp_s = ctx->t2_comp_s;
+    a.t2_nitem = ctx->t2_nitem;
+    a.t2_items = ctx->t2_items;
     a.t2_loc = ctx->t2_loc;
     a.t2_tot = ctx->t2_tot;
   }

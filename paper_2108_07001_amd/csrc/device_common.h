@@ -52,11 +52,12 @@ struct DemapArgs {
   unsigned int* t2_count;           // [S][waves]: tiles listed by each wave of the launch
   double* t2_partials;              // [S][4][gridDim.x], as partials, from the second tier
   int t2_tpw;                       // list slots per (SNR point, wave)
-  // the lists gathered into one launch-wide list, for a balanced second tier
-  unsigned long long* t2_comp;      // entries in (SNR point, wave, slot) order
-  unsigned char* t2_comp_s;         // SNR point of each gathered entry
-  unsigned int* t2_loc;             // [S][waves]: offset of each wave's list within its SNR point
-  unsigned int* t2_tot;             // [S]: entries listed at each SNR point
+  unsigned int* t2_nitem;           // [S][waves]: samples flagged in each wave's list
+  // the flagged samples gathered into one dense launch-wide list: each SNR
+  // point's run in (wave, slot, lane) order, padded to a multiple of 32
+  uint32_t* t2_items;               // sample indices
+  unsigned int* t2_loc;             // [S][waves]: offset of each wave's samples within its SNR run
+  unsigned int* t2_tot;             // [S]: samples flagged at each SNR point
   SnrTable snr;
 };
 

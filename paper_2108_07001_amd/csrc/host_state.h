@@ -35,10 +35,11 @@ struct air_ctx {
   double* t2_partials = nullptr; // kMaxSnrPerLaunch x 4 x kMaxGrid
   int64_t t2_slots = 0;          // capacity of t2_list
   int64_t t2_counts = 0;         // capacity of t2_count
-  // the same entries gathered into one list (capacity t2_slots), the
-  // per-wave offsets (capacity t2_counts) and per-SNR totals
-  unsigned long long* t2_comp = nullptr;
-  unsigned char* t2_comp_s = nullptr;
+  // flagged samples per wave (capacity t2_counts), the dense list of those
+  // samples (capacity 32 t2_slots), the per-wave offsets (capacity
+  // t2_counts) and per-SNR totals
+  unsigned int* t2_nitem = nullptr;
+  uint32_t* t2_items = nullptr;
   unsigned int* t2_loc = nullptr;
   unsigned int* t2_tot = nullptr; // kMaxSnrPerLaunch
   // optional timing of the demapping kernels (air_set_timing)

@@ -147,8 +147,11 @@ struct TileInput {
   // of draining all of them. setup() uses t and z only for valid samples (and
   // t only when there are transmitted indices).
   __device__ __forceinline__ void fetch(const SampleParams& p, int64_t st, int j) {
-    const int64_t n = st * 32 + j;
-    const int64_t nc = n < p.N ? n : p.N - 1;
+    fetch_n(p, st * 32 + j);
+  }
+  // sample n (any n: out-of-range indices read a clamped row)
+  __device__ __forceinline__ void fetch_n(const SampleParams& p, int64_t n) {
+    const int64_t nc = (n >= 0 && n < p.N) ? n : p.N - 1;
     const uint32_t* __restrict__ txp = p.tx ? p.tx : reinterpret_cast<const uint32_t*>(p.in);
     t = txp[nc];
     const float* __restrict__ in = p.in + nc * D;
@@ -186,9 +189,14 @@ struct SampleTile {
 
   __device__ __forceinline__ void setup(const SampleParams& p, int64_t st, int j, int h,
                                         bool flag_errors, const TileInput<D>& ti) {
+    setup_n(p, st * 32 + j, h, flag_errors, ti);
+  }
+  // sample n of this lane's column (n < 0: no sample)
+  __device__ __forceinline__ void setup_n(const SampleParams& p, int64_t sn, int h, bool flag_errors,
+                                          const TileInput<D>& ti) {
     const int M = p.M;
-    n = st * 32 + j;
-    valid = n < p.N;
+    n = sn;
+    valid = n >= 0 && n < p.N;
     tl = -1;
     if (valid && p.tx) {
       if (ti.t >= (uint32_t)M) {
@@ -577,33 +585,43 @@ static __global__ __launch_bounds__(256) void t2_scan(const unsigned int* __rest
   if (threadIdx.x == 255) tot[s] = part[255];
 }
 
-// Every listed entry copied to its place in the launch-wide list, in (SNR
-// point, wave, slot) order; one thread per (SNR point, wave).
+// Every flagged sample of the listed entries written to its place in the
+// dense launch-wide list: SNR point s's run starts at the sum of the earlier
+// runs rounded up to multiples of 32, and holds the samples in (wave, slot,
+// lane) order; one thread per (SNR point, wave).
+__host__ __device__ inline unsigned int t2_pad(unsigned int n) { return (n + 31u) & ~31u; }
+
 static __global__ __launch_bounds__(256) void t2_gather(const unsigned long long* __restrict__ list,
                                                  const unsigned int* __restrict__ counts,
                                                  const unsigned int* __restrict__ loc,
                                                  const unsigned int* __restrict__ tot, int W, int S,
-                                                 int tpw, unsigned long long* __restrict__ comp,
-                                                 unsigned char* __restrict__ comp_s) {
+                                                 int tpw, uint32_t* __restrict__ items) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)S * W) return;
   const unsigned int c = counts[i];
   if (c == 0) return;
   const int s = (int)(i / W);
-  unsigned int base = 0;
-  for (int k = 0; k < s; ++k) base += tot[k];
-  const int64_t o = (int64_t)base + loc[i];
+  int64_t base = 0;
+  for (int k = 0; k < s; ++k) base += t2_pad(tot[k]);
+  int64_t o = base + loc[i];
   const unsigned long long* src = list + i * tpw;
   for (unsigned int q = 0; q < c; ++q) {
-    comp[o + q] = src[q];
-    comp_s[o + q] = (unsigned char)s;
+    const unsigned long long ent = src[q];
+    const uint32_t tile = (uint32_t)(ent & 0xffffffffull);
+    uint32_t mask = (uint32_t)(ent >> 32);
+    while (mask) {
+      const int b = __builtin_ctz(mask);
+      items[o++] = tile * 32u + (uint32_t)b;
+      mask &= mask - 1u;
+    }
   }
 }
 
-// Second tier: every listed (SNR, sample tile) is re-formed in the FP64 frame.
-// The gathered list is dealt out to the waves round-robin, so the work is
-// spread evenly whatever waves of the first tier listed it; each wave sums
-// its entries per SNR point, and the block reduces its waves in a fixed order.
+// Second tier: the flagged samples, 32 to a tile in the dense list, are
+// re-formed in the FP64 frame. The tiles are dealt out to the waves
+// round-robin, so the work is spread evenly whatever waves of the first tier
+// listed it; each wave sums its samples per SNR point, and the block reduces
+// its waves in a fixed order.
 template <int D, bool BF, bool HALF, bool TBL>
 __global__ __launch_bounds__(256) void demap_mfma_t2(const DemapArgs a,
                                                      const typename MfmaOp<BF>::vec* __restrict__ rec,
@@ -643,13 +661,18 @@ __global__ __launch_bounds__(256) void demap_mfma_t2(const DemapArgs a,
   const int64_t wstride = (int64_t)gridDim.x * waves;
   const int64_t wgid = (int64_t)blockIdx.x * waves + wave;
 
-  // total of the gathered list (lane s holds SNR point s's count)
+  // the SNR runs of the dense list: lane s holds run s's padded start and its
+  // sample count; T tiles in all
   const unsigned int tot_l = lane < S ? a.t2_tot[lane] : 0u;
-  uint64_t E = 0;
-  for (int s = 0; s < S; ++s) E += __builtin_amdgcn_readlane(tot_l, s);
-  // wave w takes entries w, w + waves, ...: every wave gets a share of every
-  // SNR point (the high ones cost far more per entry), in increasing order
-  const int64_t nmine = (int64_t)E > wgid ? ((int64_t)E - wgid + wstride - 1) / wstride : 0;
+  uint64_t pstart_l = 0, run = 0;
+  for (int s = 0; s < S; ++s) {
+    if (lane == s) pstart_l = run;
+    run += t2_pad(__builtin_amdgcn_readlane(tot_l, s));
+  }
+  const int64_t T = (int64_t)(run >> 5);
+  // wave w takes tiles w, w + waves, ...: every wave gets a share of every
+  // SNR point (the high ones cost far more per sample), in increasing order
+  const int64_t nmine = T > wgid ? (T - wgid + wstride - 1) / wstride : 0;
   double* wacc = acc_lds + (int64_t)wave * S * 4;
   for (int i = lane; i < S * 4; i += 64) wacc[i] = 0.0;
   int s_cur = -1;
@@ -665,36 +688,35 @@ __global__ __launch_bounds__(256) void demap_mfma_t2(const DemapArgs a,
     }
     au = av = auu = avv = 0.0;
   };
-  unsigned long long ents = 0;          // entries b .. b + 63, lane i holding b + i
-  unsigned int ss = 0;                  // and their SNR points
   unsigned long long items = 0;         // flagged samples this wave finishes
   unsigned long long exact = 0;         // of those, the ones that needed the exact path
   for (int64_t r = 0; r < nmine; ++r) {
-    const int k = (int)(r & 63);
-    if (k == 0) {
-      const bool in = r + lane < nmine;
-      const int64_t e = wgid + (r + lane) * wstride;
-      ents = in ? a.t2_comp[e] : 0ull;
-      ss = in ? (unsigned int)a.t2_comp_s[e] : 0u;
-    }
-    const unsigned long long ent =
-        ((unsigned long long)__builtin_amdgcn_readlane((unsigned)(ents >> 32), k) << 32) |
-        (unsigned long long)__builtin_amdgcn_readlane((unsigned)ents, k);
-    const int s = (int)__builtin_amdgcn_readlane(ss, k);
+    const int64_t q = wgid + r * wstride;
+    const uint64_t p0 = (uint64_t)q * 32u;
+    // the run holding this tile: the last non-empty s whose padded start is
+    // <= p0 (tiles lie inside the runs, which are multiples of 32 long)
+    const unsigned long long in_run =
+        __ballot(lane < S && pstart_l <= p0 && tot_l > 0u) & ((S < 64) ? ((1ull << S) - 1ull) : ~0ull);
+    const int s = 63 - __builtin_clzll(in_run);
     if (s != s_cur) {
       if (s_cur >= 0) flush();
       s_cur = s;
     }
-    const int64_t st = (int64_t)(ent & 0xffffffffull);
-    const uint32_t mask = (uint32_t)(ent >> 32);
-    items += (unsigned long long)__builtin_popcount(mask);
+    const uint64_t start = ((uint64_t)__builtin_amdgcn_readlane((unsigned)(pstart_l >> 32), s) << 32) |
+                           (uint64_t)__builtin_amdgcn_readlane((unsigned)pstart_l, s);
+    const unsigned int cnt = __builtin_amdgcn_readlane(tot_l, s);
+    const uint64_t pos = p0 + (uint64_t)j;
+    const bool has = pos - start < (uint64_t)cnt;
+    const int64_t sn = has ? (int64_t)a.t2_items[pos] : -1;
+    items += (unsigned long long)__builtin_popcountll(__ballot(has && h == 0));
     const SampleParams sp = sample_params(a, s);
     TileInput<D> ti;
-    ti.load(sp, tb, st, j);
+    ti.fetch_n(sp, sn);
+    ti.resolve(sp, tb);
     ST smp;
-    smp.setup(sp, st, j, h, false, ti);
+    smp.setup_n(sp, sn, h, false, ti);
 
-    const bool flagged = (mask >> j) & 1u;
+    const bool flagged = smp.valid;
     float* lout = (llr && smp.valid) ? llr + (int64_t)s * a.llr_stride_s + smp.n * m : nullptr;
     float u, v;
     ExactArgs<float> ex = exact_args<float>(a, s);

@@ -386,6 +386,7 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
     double au = 0.0, av = 0.0, auu = 0.0, avv = 0.0;
     unsigned long long* slots = a.t2_list + ((int64_t)s * wstride + wgid) * a.t2_tpw;
     int nlisted = 0;
+    unsigned int nflag = 0;                // samples flagged in those entries
     const SampleParams sp = sample_params(a, s);
     const int64_t q0 = (wgid + ((((int64_t)s * rem) % wstride) & ~(int64_t)31)) % wstride;
     RawInput<D> curA, curB, nxtA, nxtB;
@@ -576,6 +577,7 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
       const bool need2 = live && starved;
       const unsigned long long bm = __ballot(need2);
       const unsigned long long mlo = bm & 0xffffffffull, mhi = bm >> 32;
+      nflag += __builtin_popcountll(bm);
       if (mlo) {
         if (lane == 0) slots[nlisted] = (mlo << 32) | (unsigned long long)(2 * q);
         ++nlisted;
@@ -599,7 +601,10 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
       const double wd = wave_sum((double)nlisted);
       if (lane == 0 && wd > 0.0) atomicAdd(a.recomputed, (unsigned long long)wd);
     } else {
-      if (lane == 0) a.t2_count[(int64_t)s * wstride + wgid] = (unsigned int)nlisted;
+      if (lane == 0) {
+        a.t2_count[(int64_t)s * wstride + wgid] = (unsigned int)nlisted;
+        a.t2_nitem[(int64_t)s * wstride + wgid] = nflag;
+      }
     }
     const double w0 = wave_sum(au), w1 = wave_sum(av);
     const double w2 = wave_sum(auu), w3 = wave_sum(avv);
@@ -626,10 +631,10 @@ __host__ __device__ inline int t2_grid(int grid) { return grid < 512 ? grid : 51
 // Offsets and the gathered list of the first tier's tier-2 entries.
 inline void launch_t2_gather(const DemapArgs& a, int grid, hipStream_t st) {
   const int W = grid * 4;
-  hipLaunchKernelGGL(t2_scan, dim3(a.S), dim3(256), 0, st, a.t2_count, W, a.t2_loc, a.t2_tot);
+  hipLaunchKernelGGL(t2_scan, dim3(a.S), dim3(256), 0, st, a.t2_nitem, W, a.t2_loc, a.t2_tot);
   const int64_t n = (int64_t)a.S * W;
   hipLaunchKernelGGL(t2_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a.t2_list, a.t2_count,
-                     a.t2_loc, a.t2_tot, W, a.S, a.t2_tpw, a.t2_comp, a.t2_comp_s);
+                     a.t2_loc, a.t2_tot, W, a.S, a.t2_tpw, a.t2_items);
 }
 
 // The wide first tier (exact or max-log) in the variant the constellation
