@@ -389,22 +389,22 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
     unsigned int nflag = 0;                // samples flagged in those entries
     const SampleParams sp = sample_params(a, s);
     const int64_t q0 = (wgid + ((((int64_t)s * rem) % wstride) & ~(int64_t)31)) % wstride;
-    RawInput<D> curA, curB, nxtA, nxtB;
+    RawInput<D> inA, inB;
     if (q0 < npairs) {
-      curA.fetch(sp, 2 * q0, j);
-      curB.fetch(sp, 2 * q0 + 1, j);
+      inA.fetch(sp, 2 * q0, j);
+      inB.fetch(sp, 2 * q0 + 1, j);
     }
     for (int64_t q = q0; q < npairs; q += wstride) {
-      {
-        const int64_t qn = q + wstride < npairs ? q + wstride : npairs - 1;
-        nxtA.fetch(sp, 2 * qn, j);          // next round's inputs, ahead of use
-        nxtB.fetch(sp, 2 * qn + 1, j);
-      }
       WideSample<D> smA, smB;
-      smA.setup(sp, tb, 2 * q, j, s == 0 && h == 0, curA);
-      smB.setup(sp, tb, 2 * q + 1, j, s == 0 && h == 0, curB);
-      curA = nxtA;
-      curB = nxtB;
+      smA.setup(sp, tb, 2 * q, j, s == 0 && h == 0, inA);
+      smB.setup(sp, tb, 2 * q + 1, j, s == 0 && h == 0, inB);
+      {
+        // the next round's inputs, loaded into the registers just consumed
+        // (no copy between buffers) a round ahead of use
+        const int64_t qn = q + wstride < npairs ? q + wstride : npairs - 1;
+        inA.fetch(sp, 2 * qn, j);
+        inB.fetch(sp, 2 * qn + 1, j);
+      }
       OP opA, opB;
       opA.build(smA.y, sp.c, m, h);
       opB.build(smB.y, sp.c, m, h);
