@@ -86,7 +86,9 @@ air_status air_create(air_ctx **out, int device, void *hip_stream);
 /* Release a context and its workspace (synchronises its stream first). NULL is ignored. */
 void air_destroy(air_ctx *ctx);
 
-/* Issue subsequent work on another stream of the same device. */
+/* Issue subsequent work on another stream of the same device. Waits first for
+ * the work already issued on the current stream (the next call reuses the
+ * context's workspace); returns AIR_E_DEVICE if that wait fails. */
 air_status air_set_stream(air_ctx *ctx, void *hip_stream);
 
 /* Message describing the last failure on this context ("" if none). Owned by the context. */

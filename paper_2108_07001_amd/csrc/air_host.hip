@@ -95,12 +95,13 @@ static int vec_grid(int64_t N) {
 // reduces SNR point s; wave q of it sums quantity q over the demapping blocks
 // (lane l takes blocks l, l + 64, ...; then a fixed butterfly), so the result
 // does not depend on timing. stats[4 s + q] = MI, GMI, SE_MI, SE_GMI; NaN if
-// a tx index was invalid. Block 0 folds this call's error into the sticky word.
+// a tx index was invalid. Block 0 folds this call's error into the sticky word
+// and zeroes the next call's words.
 __global__ __launch_bounds__(256) void finish_kernel(const double* __restrict__ partials,
                                                      const double* __restrict__ t2_partials,
                                                      int nblocks, int nblocks2, int64_t N, int M, int m,
                                                      double* stats, const CallWords* call,
-                                                     int* sticky, int no_mi) {
+                                                     CallWords* next, int* sticky, int no_mi) {
   __shared__ double sums[4];
   const int s = blockIdx.x;
   const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -145,14 +146,20 @@ __global__ __launch_bounds__(256) void finish_kernel(const double* __restrict__ 
       stats[4 * s + 2] = se_mi;
       stats[4 * s + 3] = se_gmi;
     }
-    if (s == 0 && bad) atomicOr(sticky, bad);
+    if (s == 0) {
+      if (bad) atomicOr(sticky, bad);
+      clear_call_words(next);
+    }
   }
 }
 
-// Folds a call's tx-range error into the sticky word (calls without a
-// reduction kernel of their own).
-__global__ void fold_error_kernel(const CallWords* call, int* sticky) {
-  if (threadIdx.x == 0 && call->err) atomicOr(sticky, call->err);
+// Folds a call's tx-range error into the sticky word and zeroes the next
+// call's words (calls without a reduction kernel of their own).
+__global__ void fold_error_kernel(const CallWords* call, CallWords* next, int* sticky) {
+  if (threadIdx.x == 0) {
+    if (call->err) atomicOr(sticky, call->err);
+    clear_call_words(next);
+  }
 }
 
 }  // namespace air
@@ -234,15 +241,11 @@ void fill_snr(SnrTable& t, const air_const* c, const double* snr_db, int S, bool
 // grows on demand and is kept, so repeated calls of one size allocate nothing.
 void free_t2(air_ctx* ctx) {
   (void)hipFree(ctx->t2_list);
-  (void)hipFree(ctx->t2_count);
   (void)hipFree(ctx->t2_nitem);
   (void)hipFree(ctx->t2_items);
-  (void)hipFree(ctx->t2_loc);
   ctx->t2_list = nullptr;
-  ctx->t2_count = nullptr;
   ctx->t2_nitem = nullptr;
   ctx->t2_items = nullptr;
-  ctx->t2_loc = nullptr;
   ctx->t2_slots = ctx->t2_counts = 0;
 }
 
@@ -251,12 +254,10 @@ air_status ensure_t2(air_ctx* ctx, int64_t slots, int64_t counts) {
   (void)hipStreamSynchronize(ctx->stream);
   free_t2(ctx);
   hipError_t e = hipMalloc(&ctx->t2_list, sizeof(unsigned long long) * slots);
-  if (e == hipSuccess) e = hipMalloc(&ctx->t2_count, sizeof(unsigned int) * counts);
   if (e == hipSuccess) e = hipMalloc(&ctx->t2_nitem, sizeof(unsigned int) * counts);
-  // every slot lists one 32-sample tile, so the dense list holds at most 32
-  // samples per slot (the padding of each SNR run to 32 fits in the same bound)
+  // every slot lists one 32-sample tile, so an SNR point's gathered samples
+  // fit in 32 entries per slot of that point
   if (e == hipSuccess) e = hipMalloc(&ctx->t2_items, sizeof(uint32_t) * 32 * slots);
-  if (e == hipSuccess) e = hipMalloc(&ctx->t2_loc, sizeof(unsigned int) * counts);
   if (e != hipSuccess) {
     free_t2(ctx);
     return hip_fail(ctx, e, "second-tier workspace");
@@ -264,6 +265,18 @@ air_status ensure_t2(air_ctx* ctx, int64_t slots, int64_t counts) {
   ctx->t2_slots = slots;
   ctx->t2_counts = counts;
   return AIR_OK;
+}
+
+// The words of a new call: the slot that the previous call's final kernel
+// zeroed or, when that kernel was not issued (a call that failed part-way), a
+// slot zeroed here. *next receives the slot this call's final kernel zeroes.
+hipError_t begin_call(air_ctx* ctx, CallWords** next) {
+  CallWords* cur = ctx->call == ctx->calls ? ctx->calls + 1 : ctx->calls;
+  *next = cur == ctx->calls ? ctx->calls + 1 : ctx->calls;
+  ctx->call = cur;
+  const bool zeroed = ctx->next_zeroed;
+  ctx->next_zeroed = false;
+  return zeroed ? hipSuccess : hipMemsetAsync(cur, 0, sizeof(CallWords), ctx->stream);
 }
 
 bool prec_ok(air_prec p) { return p == AIR_FP64 || p == AIR_FP32 || p == AIR_BF16X3 || p == AIR_FP16X3; }
@@ -303,9 +316,6 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
   std::memset(&a, 0, sizeof(a));
   a.in = in;
   a.tx = tx;
-  a.err = &ctx->call->err;
-  a.recomputed = &ctx->call->recomputed;
-  a.exact = &ctx->call->exact;
   a.partials = ctx->partials;
   a.xl = fp64 ? (const void*)c->x64 : (const void*)c->x32;
   a.lab = c->lab;
@@ -327,16 +337,19 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
     const air_status st = ensure_t2(ctx, sl * waves * tpw, sl * waves);
     if (st != AIR_OK) return st;
     a.t2_list = ctx->t2_list;
-    a.t2_count = ctx->t2_count;
     a.t2_partials = ctx->t2_partials;
     a.t2_tpw = (int)tpw;
     a.t2_nitem = ctx->t2_nitem;
     a.t2_items = ctx->t2_items;
-    a.t2_loc = ctx->t2_loc;
+    a.t2_cap = waves * tpw * 32;
     a.t2_tot = ctx->t2_tot;
   }
-  hipError_t e = hipMemsetAsync(ctx->call, 0, sizeof(CallWords), ctx->stream);
+  CallWords* next = nullptr;
+  hipError_t e = begin_call(ctx, &next);
   if (e != hipSuccess) return hip_fail(ctx, e, "clear call words");
+  a.err = &ctx->call->err;
+  a.recomputed = &ctx->call->recomputed;
+  a.exact = &ctx->call->exact;
   for (int s0 = 0; s0 < S; s0 += kMaxSnrPerLaunch) {
     const int ns = (S - s0 < kMaxSnrPerLaunch) ? S - s0 : kMaxSnrPerLaunch;
     a.S = ns;
@@ -370,10 +383,11 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
     }
     hipLaunchKernelGGL(finish_kernel, dim3(ns), dim3(256), 0, ctx->stream, ctx->partials,
                        tier2 ? ctx->t2_partials : nullptr, grid, t2_grid(grid), N, c->M, c->m,
-                       stats ? stats + 4 * s0 : nullptr, ctx->call, ctx->sticky, maxlog ? 1 : 0);
+                       stats ? stats + 4 * s0 : nullptr, ctx->call, next, ctx->sticky, maxlog ? 1 : 0);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(ctx, e, "reduction kernel launch");
   }
+  ctx->next_zeroed = true;
   ctx->err.clear();
   return AIR_OK;
 }
@@ -405,11 +419,12 @@ air_status run_hd(air_ctx* ctx, const air_const* c, const float* in, const uint3
   a.xl = c->x32;
   a.lab = c->lab;
   a.pos = c->pos;
-  a.err = &ctx->call->err;
   a.N = N;
   a.M = c->M;
   a.sweep = sweep;
-  hipError_t e = hipMemsetAsync(ctx->call, 0, sizeof(CallWords), ctx->stream);
+  CallWords* next = nullptr;
+  hipError_t e = begin_call(ctx, &next);
+  a.err = &ctx->call->err;
   if (e == hipSuccess && counts)
     e = hipMemsetAsync(counts, 0, sizeof(uint64_t) * 2 * (size_t)S, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "clear counters");
@@ -428,9 +443,10 @@ air_status run_hd(air_ctx* ctx, const air_const* c, const float* in, const uint3
     if (e != hipSuccess) return hip_fail(ctx, e, "hard-decision kernel launch");
   }
   // a tx-range error is reported by air_sync like the demapping calls'
-  hipLaunchKernelGGL(fold_error_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->call, ctx->sticky);
+  hipLaunchKernelGGL(fold_error_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->call, next, ctx->sticky);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(ctx, e, "error fold launch");
+  ctx->next_zeroed = true;
   ctx->err.clear();
   return AIR_OK;
 }
@@ -448,7 +464,8 @@ air_status run_noise_var(air_ctx* ctx, const air_const* c, const void* Y, const 
   if (!is_device_ptr(ctx, Y)) return fail(ctx, AIR_E_INVAL, "Y_dev is not device memory of this context");
   if (!is_device_ptr(ctx, tx)) return fail(ctx, AIR_E_INVAL, "tx_dev is not device memory of this context");
   if (!is_device_ptr(ctx, var)) return fail(ctx, AIR_E_INVAL, "var_dev is not device memory of this context");
-  hipError_t e = hipMemsetAsync(ctx->call, 0, sizeof(CallWords), ctx->stream);
+  CallWords* next = nullptr;
+  hipError_t e = begin_call(ctx, &next);
   if (e != hipSuccess) return hip_fail(ctx, e, "clear call words");
   const int grid = vec_grid(N);     // <= kMaxGrid: D x grid partials fit the workspace
   if (prec == AIR_FP64)
@@ -462,9 +479,10 @@ air_status run_noise_var(air_ctx* ctx, const air_const* c, const void* Y, const 
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(ctx, e, "noise estimate launch");
   hipLaunchKernelGGL(noise_var_finish, dim3(1), dim3(64), 0, ctx->stream, ctx->partials, grid, c->D, N,
-                     var, &ctx->call->err, ctx->sticky);
+                     var, &ctx->call->err, next, ctx->sticky);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(ctx, e, "noise estimate reduction launch");
+  ctx->next_zeroed = true;
   ctx->err.clear();
   return AIR_OK;
 }
@@ -487,9 +505,10 @@ air_status air_create(air_ctx** out, int device, void* hip_stream) {
     hipError_t e = hipMalloc(&ctx->partials, sizeof(double) * kMaxGrid * kMaxSnrPerLaunch * 4);
     if (e == hipSuccess) e = hipMalloc(&ctx->t2_partials, sizeof(double) * kMaxGrid * kMaxSnrPerLaunch * 4);
     if (e == hipSuccess) e = hipMalloc(&ctx->t2_tot, sizeof(unsigned int) * kMaxSnrPerLaunch);
-    if (e == hipSuccess) e = hipMalloc(&ctx->call, sizeof(CallWords));
+    if (e == hipSuccess) e = hipMalloc(&ctx->calls, 2 * sizeof(CallWords));
     if (e == hipSuccess) e = hipMalloc(&ctx->sticky, sizeof(int));
-    if (e == hipSuccess) e = hipMemset(ctx->call, 0, sizeof(CallWords));
+    if (e == hipSuccess) e = hipMemset(ctx->calls, 0, 2 * sizeof(CallWords));
+    ctx->call = ctx->calls;
     if (e == hipSuccess) e = hipMemset(ctx->sticky, 0, sizeof(int));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -508,7 +527,7 @@ void air_destroy(air_ctx* ctx) {
   DeviceGuard g(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   (void)hipFree(ctx->partials);
-  (void)hipFree(ctx->call);
+  (void)hipFree(ctx->calls);
   (void)hipFree(ctx->sticky);
   free_t2(ctx);
   (void)hipFree(ctx->t2_partials);
@@ -519,6 +538,12 @@ void air_destroy(air_ctx* ctx) {
 
 air_status air_set_stream(air_ctx* ctx, void* hip_stream) {
   if (!ctx) return AIR_E_INVAL;
+  // the next call reuses the workspace and call words of the work already
+  // issued, so that work finishes first
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, AIR_E_DEVICE, "cannot select the context's device");
+  const hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "synchronize the previous stream");
   ctx->stream = (hipStream_t)hip_stream;
   return AIR_OK;
 }

@@ -62,10 +62,10 @@ __global__ __launch_bounds__(kBlock) void noise_var_kernel(const T* __restrict__
 // One wave: dimension d's block partials (lane l takes blocks l, l + 64, ...,
 // then a fixed butterfly); var[d] = sum / N, var[D] = the mean of the D
 // values. NaN everywhere if a transmitted index was out of range; the error
-// is folded into the sticky word.
+// is folded into the sticky word. Lane 0 zeroes the next call's words.
 __global__ __launch_bounds__(64) void noise_var_finish(const double* __restrict__ partials, int nblocks,
                                                        int D, int64_t N, double* __restrict__ var,
-                                                       const int* err, int* sticky) {
+                                                       const int* err, CallWords* next, int* sticky) {
   const int lane = threadIdx.x;
   const bool bad = *err != 0;
   double all = 0.0;
@@ -79,6 +79,7 @@ __global__ __launch_bounds__(64) void noise_var_finish(const double* __restrict_
   if (lane == 0) {
     var[D] = bad ? __builtin_nan("") : all / (double)D;
     if (bad) atomicOr(sticky, 1);
+    clear_call_words(next);
   }
 }
 

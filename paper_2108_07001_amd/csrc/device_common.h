@@ -24,6 +24,25 @@ constexpr int kMaxD = 16;
 constexpr int kBlock = 256;         // threads per block of the vector kernels
 constexpr int kMaxGrid = 1024;      // upper bound on blocks of one demapping launch
 
+// Per-call device words: the tx-range error of a call and the number of items
+// sent through the exact path; zero when the call starts.
+struct CallWords {
+  int err;
+  int pad;
+  unsigned long long recomputed;   // items finished outside the first tier's sums
+  unsigned long long exact;        // of those, items that needed the exact path
+};
+
+// Zeroes the words of the next call (one thread).
+__device__ inline void clear_call_words(CallWords* next) {
+  if (next) {
+    next->err = 0;
+    next->pad = 0;
+    next->recomputed = 0ull;
+    next->exact = 0ull;
+  }
+}
+
 // Per-SNR scalars of one launch, passed by value in the kernel arguments.
 struct SnrTable {
   double sigma[kMaxSnrPerLaunch];   // noise standard deviation per real dimension
@@ -49,14 +68,13 @@ struct DemapArgs {
   int sweep;                        // 1: y = x_t + sigma_s z from `in`
   // second tier of the matrix-core path (unused by the vector kernels)
   unsigned long long* t2_list;      // [S][waves][tpw]: sample tile (32 bits) | lane mask (32)
-  unsigned int* t2_count;           // [S][waves]: tiles listed by each wave of the launch
   double* t2_partials;              // [S][4][gridDim.x], as partials, from the second tier
   int t2_tpw;                       // list slots per (SNR point, wave)
   unsigned int* t2_nitem;           // [S][waves]: samples flagged in each wave's list
-  // the flagged samples gathered into one dense launch-wide list: each SNR
-  // point's run in (wave, slot, lane) order, padded to a multiple of 32
+  // the flagged samples gathered per SNR point: point s's samples, in (wave,
+  // slot, lane) order, from entry s * t2_cap of t2_items
   uint32_t* t2_items;               // sample indices
-  unsigned int* t2_loc;             // [S][waves]: offset of each wave's samples within its SNR run
+  int64_t t2_cap;                   // entries of t2_items per SNR point (waves x tpw x 32)
   unsigned int* t2_tot;             // [S]: samples flagged at each SNR point
   SnrTable snr;
 };

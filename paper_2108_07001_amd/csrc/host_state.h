@@ -11,36 +11,26 @@
 #include <string>
 #include <vector>
 
-namespace air {
-// Per-call device words: the tx-range error of this call and the number of
-// items sent through the exact path; cleared at the start of every call.
-struct CallWords {
-  int err;
-  int pad;
-  unsigned long long recomputed;   // items finished outside the first tier's sums
-  unsigned long long exact;        // of those, items that needed the exact path
-};
-}  // namespace air
-
 struct air_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
   double* partials = nullptr;    // kMaxSnrPerLaunch x 4 x kMaxGrid
-  air::CallWords* call = nullptr;  // this call's error word and exact-path count
+  // Per-call words in two slots that calls use in turn: a call's final
+  // kernel zeroes the other slot, so the next call starts without a fill.
+  air::CallWords* calls = nullptr;
+  air::CallWords* call = nullptr;  // the slot of the current (or last) call
+  bool next_zeroed = true;         // the other slot is known to hold zeros
   int* sticky = nullptr;         // tx-range error seen since the last air_sync
   // second tier of the matrix-core path: per-wave tile lists and their counts
   unsigned long long* t2_list = nullptr;
-  unsigned int* t2_count = nullptr;
   double* t2_partials = nullptr; // kMaxSnrPerLaunch x 4 x kMaxGrid
   int64_t t2_slots = 0;          // capacity of t2_list
-  int64_t t2_counts = 0;         // capacity of t2_count
-  // flagged samples per wave (capacity t2_counts), the dense list of those
-  // samples (capacity 32 t2_slots), the per-wave offsets (capacity
-  // t2_counts) and per-SNR totals
+  int64_t t2_counts = 0;         // capacity of t2_nitem
+  // flagged samples per wave (capacity t2_counts), those samples gathered
+  // per SNR point (capacity 32 t2_slots) and per-SNR totals
   unsigned int* t2_nitem = nullptr;
   uint32_t* t2_items = nullptr;
-  unsigned int* t2_loc = nullptr;
   unsigned int* t2_tot = nullptr; // kMaxSnrPerLaunch
   // optional timing of the demapping kernels (air_set_timing)
   bool timing = false;

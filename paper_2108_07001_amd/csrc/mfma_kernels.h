@@ -549,75 +549,71 @@ __device__ __forceinline__ bool tier2_tile(const SampleTile<D, BF>& smp, const T
   return flagged && st2 && h == 0;
 }
 
-// Offsets of the per-wave tier-2 lists of SNR point s (block s): an exclusive
-// scan over the first tier's waves in wave order, and the point's total.
-static __global__ __launch_bounds__(256) void t2_scan(const unsigned int* __restrict__ counts, int W,
-                                               unsigned int* __restrict__ loc,
-                                               unsigned int* __restrict__ tot) {
-  constexpr int kPer = 16;                 // W <= 256 * kPer (kMaxGrid waves of 4)
-  __shared__ unsigned int part[256];
-  const int s = blockIdx.x;
-  const unsigned int* c = counts + (int64_t)s * W;
-  const int per = (W + 255) / 256;
-  const int w0 = threadIdx.x * per;
-  // all of this thread's counts in flight at once, then summed in order
-  unsigned int cv[kPer];
-#pragma unroll
-  for (int i = 0; i < kPer; ++i) cv[i] = (i < per && w0 + i < W) ? c[w0 + i] : 0u;
-  unsigned int sum = 0;
-#pragma unroll
-  for (int i = 0; i < kPer; ++i) sum += cv[i];
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const unsigned int v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
-  }
-  unsigned int run = part[threadIdx.x] - sum;
-#pragma unroll
-  for (int i = 0; i < kPer; ++i)
-    if (i < per && w0 + i < W) {
-      loc[(int64_t)s * W + w0 + i] = run;
-      run += cv[i];
-    }
-  if (threadIdx.x == 255) tot[s] = part[255];
-}
-
-// Every flagged sample of the listed entries written to its place in the
-// dense launch-wide list: SNR point s's run starts at the sum of the earlier
-// runs rounded up to multiples of 32, and holds the samples in (wave, slot,
-// lane) order; one thread per (SNR point, wave).
 __host__ __device__ inline unsigned int t2_pad(unsigned int n) { return (n + 31u) & ~31u; }
 
-static __global__ __launch_bounds__(256) void t2_gather(const unsigned long long* __restrict__ list,
-                                                 const unsigned int* __restrict__ counts,
-                                                 const unsigned int* __restrict__ loc,
-                                                 const unsigned int* __restrict__ tot, int W, int S,
-                                                 int tpw, uint32_t* __restrict__ items) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)S * W) return;
-  const unsigned int c = counts[i];
-  if (c == 0) return;
-  const int s = (int)(i / W);
-  int64_t base = 0;
-  for (int k = 0; k < s; ++k) base += t2_pad(tot[k]);
-  int64_t o = base + loc[i];
-  const unsigned long long* src = list + i * tpw;
-  for (unsigned int q = 0; q < c; ++q) {
+// The flagged samples of the first tier gathered per SNR point: point s's
+// samples go to entries s * cap, s * cap + 1, ... of `items` in (wave, slot,
+// lane) order. Block (b, s) places waves 256 b ... 256 b + 255 of point s:
+// the flagged counts of the point's earlier waves are summed, its own are
+// scanned, and each thread then expands its wave's list entries (a sample
+// tile and the mask of its flagged lanes; only non-empty masks are listed)
+// into sample indices. The point's last block writes the point's total.
+constexpr int kCollectPre = 16;            // earlier 256-wave groups one block sums
+static_assert(kMaxGrid * 4 <= 256 * kCollectPre, "a demapping launch has too many waves to collect");
+
+static __global__ __launch_bounds__(256) void t2_collect(const unsigned int* __restrict__ nitem,
+                                                  const unsigned long long* __restrict__ list, int W,
+                                                  int tpw, int64_t cap, unsigned int* __restrict__ tot,
+                                                  uint32_t* __restrict__ items) {
+  __shared__ unsigned int wpart[2][4];
+  const int b = blockIdx.x;
+  const int s = blockIdx.y;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wave = t >> 6;
+  const unsigned int* c = nitem + (int64_t)s * W;
+  // every count this thread needs in flight at once
+  unsigned int pv[kCollectPre];
+#pragma unroll
+  for (int i = 0; i < kCollectPre; ++i) pv[i] = i < b ? c[t + 256 * i] : 0u;
+  const int w = b * 256 + t;
+  const unsigned int own = w < W ? c[w] : 0u;
+  unsigned int pre = 0;
+#pragma unroll
+  for (int i = 0; i < kCollectPre; ++i) pre += pv[i];
+  unsigned int inc = own;                  // inclusive scan over the wave's lanes
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    pre += __shfl_xor(pre, off);
+    const unsigned int v = __shfl_up(inc, off);
+    if (lane >= off) inc += v;
+  }
+  if (lane == 63) {
+    wpart[0][wave] = pre;
+    wpart[1][wave] = inc;
+  }
+  __syncthreads();
+  unsigned int base = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) base += wpart[0][k] + (k < wave ? wpart[1][k] : 0u);
+  if (b == (int)gridDim.x - 1 && t == 255) tot[s] = base + inc;
+  if (own == 0) return;
+  uint32_t* out = items + (int64_t)s * cap + (base + inc - own);
+  const unsigned long long* src = list + ((int64_t)s * W + w) * tpw;
+  unsigned int got = 0;
+  for (int q = 0; q < tpw && got < own; ++q) {
     const unsigned long long ent = src[q];
     const uint32_t tile = (uint32_t)(ent & 0xffffffffull);
     uint32_t mask = (uint32_t)(ent >> 32);
-    while (mask) {
-      const int b = __builtin_ctz(mask);
-      items[o++] = tile * 32u + (uint32_t)b;
+    while (mask && got < own) {
+      out[got++] = tile * 32u + (uint32_t)__builtin_ctz(mask);
       mask &= mask - 1u;
     }
   }
 }
 
-// Second tier: the flagged samples, 32 to a tile in the dense list, are
+// Second tier: the flagged samples, 32 to a tile (the SNR points' runs, each
+// padded to a multiple of 32, numbered as one sequence of tiles), are
 // re-formed in the FP64 frame. The tiles are dealt out to the waves
 // round-robin, so the work is spread evenly whatever waves of the first tier
 // listed it; each wave sums its samples per SNR point, and the block reduces
@@ -661,7 +657,7 @@ __global__ __launch_bounds__(256) void demap_mfma_t2(const DemapArgs a,
   const int64_t wstride = (int64_t)gridDim.x * waves;
   const int64_t wgid = (int64_t)blockIdx.x * waves + wave;
 
-  // the SNR runs of the dense list: lane s holds run s's padded start and its
+  // the SNR runs in the tile sequence: lane s holds run s's padded start and its
   // sample count; T tiles in all
   const unsigned int tot_l = lane < S ? a.t2_tot[lane] : 0u;
   uint64_t pstart_l = 0, run = 0;
@@ -707,7 +703,7 @@ __global__ __launch_bounds__(256) void demap_mfma_t2(const DemapArgs a,
     const unsigned int cnt = __builtin_amdgcn_readlane(tot_l, s);
     const uint64_t pos = p0 + (uint64_t)j;
     const bool has = pos - start < (uint64_t)cnt;
-    const int64_t sn = has ? (int64_t)a.t2_items[pos] : -1;
+    const int64_t sn = has ? (int64_t)a.t2_items[(int64_t)s * a.t2_cap + (int64_t)(pos - start)] : -1;
     items += (unsigned long long)__builtin_popcountll(__ballot(has && h == 0));
     const SampleParams sp = sample_params(a, s);
     TileInput<D> ti;

@@ -601,10 +601,7 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
       const double wd = wave_sum((double)nlisted);
       if (lane == 0 && wd > 0.0) atomicAdd(a.recomputed, (unsigned long long)wd);
     } else {
-      if (lane == 0) {
-        a.t2_count[(int64_t)s * wstride + wgid] = (unsigned int)nlisted;
-        a.t2_nitem[(int64_t)s * wstride + wgid] = nflag;
-      }
+      if (lane == 0) a.t2_nitem[(int64_t)s * wstride + wgid] = nflag;
     }
     const double w0 = wave_sum(au), w1 = wave_sum(av);
     const double w2 = wave_sum(auu), w3 = wave_sum(avv);
@@ -628,13 +625,11 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
 // chip at two waves per SIMD); the gathered list is spread over them evenly.
 __host__ __device__ inline int t2_grid(int grid) { return grid < 512 ? grid : 512; }
 
-// Offsets and the gathered list of the first tier's tier-2 entries.
-inline void launch_t2_gather(const DemapArgs& a, int grid, hipStream_t st) {
+// The first tier's flagged samples gathered per SNR point, with their counts.
+inline void launch_t2_collect(const DemapArgs& a, int grid, hipStream_t st) {
   const int W = grid * 4;
-  hipLaunchKernelGGL(t2_scan, dim3(a.S), dim3(256), 0, st, a.t2_nitem, W, a.t2_loc, a.t2_tot);
-  const int64_t n = (int64_t)a.S * W;
-  hipLaunchKernelGGL(t2_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a.t2_list, a.t2_count,
-                     a.t2_loc, a.t2_tot, W, a.S, a.t2_tpw, a.t2_items);
+  hipLaunchKernelGGL(t2_collect, dim3((unsigned)((W + 255) / 256), (unsigned)a.S), dim3(256), 0, st, a.t2_nitem,
+                     a.t2_list, W, a.t2_tpw, a.t2_cap, a.t2_tot, a.t2_items);
 }
 
 // The wide first tier (exact or max-log) in the variant the constellation
@@ -674,7 +669,7 @@ hipError_t launch_mfma_wide_td(const DemapArgs& a, const void* rec, int grid, hi
     else launch_first_tier<D, BF, true>(a, r, x, grid, st);
     return hipGetLastError();
   }
-  launch_t2_gather(a, grid, st);
+  launch_t2_collect(a, grid, st);
   const dim3 g2(t2_grid(grid));
   if (a.M == 16)
     hipLaunchKernelGGL((demap_mfma_t2<D, BF, true, true>), g2, dim3(256), acc + tbytes, st, a, r, x);
