@@ -533,7 +533,7 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
           for (int k = 0; k < kMaxBits; ++k)
             if (k < m) {
               const float lam = side[2 * k] - side[2 * k + 1];
-              if (lout) lout[k] = Real<float>::ln2() * lam;
+              if (lout) __builtin_nontemporal_store(Real<float>::ln2() * lam, lout + k);
               if (tl >= 0) v += softplus2(((tl >> k) & 1) ? lam : -lam);
             }
         } else if (valid && lout) {
@@ -566,9 +566,10 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(cons
           }
         }
         if (lout) {
+          // streamed past the caches: the LLRs are not read again here
 #pragma unroll
           for (int k = 0; k < kMaxBits; ++k)
-            if (k < m) lout[k] = L[k];
+            if (k < m) __builtin_nontemporal_store(L[k], lout + k);
         }
         u = lam_tot - Real<float>::log2(Real<float>::exp2(arg_t));
       }
