@@ -154,11 +154,12 @@ int64_t air_last_recomputed(air_ctx *ctx);
  * the vector kernels every recomputed item). Synchronises. -1 on error. */
 int64_t air_last_exact(air_ctx *ctx);
 
-/* Kernel timing for measurement tools. While enabled, every call records a
- * pair of HIP events on the context's stream around each launch of its main
- * demapping kernel: the vector kernel, or the first tier of the matrix-core
- * forms (not around their second tier or the small reduction kernel that
- * follows). Enabling or disabling discards the recorded pairs. */
+/* Kernel timing for measurement tools. While enabled, each launch of a call's
+ * main demapping kernel (the vector kernel, or the first tier of the
+ * matrix-core forms; not their second tier or the small reduction kernel that
+ * follows) sets a pair of HIP events to the kernel's own start and end
+ * (hipExtLaunchKernel: no marker commands are added to the stream). Enabling
+ * or disabling discards the recorded pairs. */
 air_status air_set_timing(air_ctx *ctx, int enable);
 
 /* Sum of the demapping-kernel durations recorded since timing was enabled or

@@ -17,8 +17,8 @@
 namespace air {
 
 // Vector-kernel launchers, one per (type, D), defined in vec_inst_*.hip.
-using VecFn = hipError_t (*)(const DemapArgs&, int, hipStream_t, bool);
-#define AIR_DECL(tag, D) hipError_t launch_vec_##tag##_d##D(const DemapArgs&, int, hipStream_t, bool);
+using VecFn = hipError_t (*)(const DemapArgs&, int, const Launch&, bool);
+#define AIR_DECL(tag, D) hipError_t launch_vec_##tag##_d##D(const DemapArgs&, int, const Launch&, bool);
 #define AIR_DECL_ALL(tag)                                                                        \
   AIR_DECL(tag, 1) AIR_DECL(tag, 2) AIR_DECL(tag, 3) AIR_DECL(tag, 4) AIR_DECL(tag, 5)          \
   AIR_DECL(tag, 6) AIR_DECL(tag, 7) AIR_DECL(tag, 8) AIR_DECL(tag, 9) AIR_DECL(tag, 10)         \
@@ -54,8 +54,8 @@ static const HdFn kHd[kMaxD + 1] = {
     launch_hd_d13, launch_hd_d14, launch_hd_d15, launch_hd_d16};
 
 // Matrix-core launchers, one per (operand type, D), defined in mfma_inst_*.hip.
-using MfmaFn = hipError_t (*)(const DemapArgs&, const void*, int, hipStream_t, int);
-#define AIR_DECL(tag, D) hipError_t launch_mfma_##tag##_d##D(const DemapArgs&, const void*, int, hipStream_t, int);
+using MfmaFn = hipError_t (*)(const DemapArgs&, const void*, int, const Launch&, int);
+#define AIR_DECL(tag, D) hipError_t launch_mfma_##tag##_d##D(const DemapArgs&, const void*, int, const Launch&, int);
 #define AIR_DECL_ALL(tag)                                                                        \
   AIR_DECL(tag, 1) AIR_DECL(tag, 2) AIR_DECL(tag, 3) AIR_DECL(tag, 4) AIR_DECL(tag, 5)          \
   AIR_DECL(tag, 6) AIR_DECL(tag, 7) AIR_DECL(tag, 8) AIR_DECL(tag, 9) AIR_DECL(tag, 10)         \
@@ -355,7 +355,8 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
     a.S = ns;
     fill_snr(a.snr, c, snr_db + s0, ns, aux);
     a.llr = llr ? (void*)((char*)llr + (size_t)s0 * N * c->m * tsz) : nullptr;
-    hipEvent_t* evp = nullptr;
+    // timed: the demapping kernel's dispatch itself sets the two events
+    Launch lt{ctx->stream, nullptr, nullptr};
     if (ctx->timing) {
       if (ctx->ev_used + 2 > ctx->ev.size()) {
         for (int k = 0; k < 2; ++k) {
@@ -365,20 +366,15 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
           ctx->ev.push_back(ev);
         }
       }
-      evp = &ctx->ev[ctx->ev_used];
+      lt.start = ctx->ev[ctx->ev_used];
+      lt.stop = ctx->ev[ctx->ev_used + 1];
       ctx->ev_used += 2;
-      e = hipEventRecord(evp[0], ctx->stream);
-      if (e != hipSuccess) return hip_fail(ctx, e, "timing event record");
     }
-    e = mfma ? mfn(a, rec, grid, ctx->stream, maxlog ? 2 : 0) : vfn(a, grid, ctx->stream, maxlog);
+    e = mfma ? mfn(a, rec, grid, lt, maxlog ? 2 : 0) : vfn(a, grid, lt, maxlog);
     if (e != hipSuccess) return hip_fail(ctx, e, "demapping kernel launch");
-    if (evp) {
-      e = hipEventRecord(evp[1], ctx->stream);
-      if (e != hipSuccess) return hip_fail(ctx, e, "timing event record");
-    }
     const bool tier2 = mfma && !maxlog;
     if (tier2) {
-      e = mfn(a, rec, grid, ctx->stream, 1);
+      e = mfn(a, rec, grid, Launch{ctx->stream, nullptr, nullptr}, 1);
       if (e != hipSuccess) return hip_fail(ctx, e, "second-tier launch");
     }
     hipLaunchKernelGGL(finish_kernel, dim3(ns), dim3(256), 0, ctx->stream, ctx->partials,

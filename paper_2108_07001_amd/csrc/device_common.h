@@ -13,6 +13,7 @@
 // its own maximum as shift (slow_rel). guard = 20 bits for FP32 (the flushed
 // mass is then < 2^-20 of the side), 60 for FP64.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -23,6 +24,23 @@ constexpr int kMaxBits = 12;        // M <= 4096
 constexpr int kMaxD = 16;
 constexpr int kBlock = 256;         // threads per block of the vector kernels
 constexpr int kMaxGrid = 1024;      // upper bound on blocks of one demapping launch
+
+// Where a demapping kernel is launched: the stream and, for a timed launch,
+// two events that take the kernel's own start and end times from its
+// dispatch (no marker commands between the kernels). Both null: untimed.
+struct Launch {
+  hipStream_t stream;
+  hipEvent_t start;
+  hipEvent_t stop;
+};
+
+template <typename F, typename... Args>
+inline void launch_kernel(const Launch& l, F kernel, dim3 grid, dim3 block, uint32_t shmem, Args... args) {
+  if (l.start || l.stop)
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, l.stream, l.start, l.stop, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, shmem, l.stream, args...);
+}
 
 // Per-call device words: the tx-range error of a call and the number of items
 // sent through the exact path; zero when the call starts.

@@ -4,8 +4,8 @@
 
 namespace air {
 #define AIR_MFMA_INST(D) \
-  hipError_t launch_mfma_f16_d##D(const DemapArgs& a, const void* rec, int g, hipStream_t s, int part) { \
-    return launch_mfma_wide_td<D, false>(a, rec, g, s, part); \
+  hipError_t launch_mfma_f16_d##D(const DemapArgs& a, const void* rec, int g, const Launch& l, int part) { \
+    return launch_mfma_wide_td<D, false>(a, rec, g, l, part); \
   }
 AIR_MFMA_INST(9)
 AIR_MFMA_INST(10)

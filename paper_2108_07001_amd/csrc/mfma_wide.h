@@ -637,28 +637,30 @@ inline void launch_t2_collect(const DemapArgs& a, int grid, hipStream_t st) {
 // size calls for.
 template <int D, bool BF, bool ML>
 void launch_first_tier(const DemapArgs& a, const typename MfmaOp<BF>::vec* r, const float* x, int grid,
-                       hipStream_t st) {
-  const size_t acc = sizeof(double) * 4 * a.S * 4;
+                       const Launch& l) {
+  const uint32_t acc = (uint32_t)(sizeof(double) * 4 * a.S * 4);
   const int64_t tbytes = table_bytes(a.M, D);
   const bool tbl = tbytes <= 40 * 1024;
+  const uint32_t lds = acc + (uint32_t)tbytes;
   // the exact-size forms hold their tables in LDS (at most 12.5 KB for M = 64)
   if (a.M == 16)
-    hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 4, ML>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
+    launch_kernel(l, demap_mfma_w<D, BF, true, 4, ML>, dim3(grid), dim3(256), lds, a, r, x);
   else if (a.M == 32)
-    hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 5, ML>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
+    launch_kernel(l, demap_mfma_w<D, BF, true, 5, ML>, dim3(grid), dim3(256), lds, a, r, x);
   else if (a.M == 64)
-    hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 6, ML>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
+    launch_kernel(l, demap_mfma_w<D, BF, true, 6, ML>, dim3(grid), dim3(256), lds, a, r, x);
   else if (tbl)
-    hipLaunchKernelGGL((demap_mfma_w<D, BF, true, 0, ML>), dim3(grid), dim3(256), acc + tbytes, st, a, r, x);
+    launch_kernel(l, demap_mfma_w<D, BF, true, 0, ML>, dim3(grid), dim3(256), lds, a, r, x);
   else
-    hipLaunchKernelGGL((demap_mfma_w<D, BF, false, 0, ML>), dim3(grid), dim3(256), acc, st, a, r, x);
+    launch_kernel(l, demap_mfma_w<D, BF, false, 0, ML>, dim3(grid), dim3(256), acc, a, r, x);
 }
 
 // One part of the matrix-core path for one (D, operand type). part 0: the
 // exact first tier; 1: the gather of its lists and the shared second tier;
-// 2: the max-log form (one kernel, no second tier).
+// 2: the max-log form (one kernel, no second tier). The events of `l` time
+// the first tier's kernel only.
 template <int D, bool BF>
-hipError_t launch_mfma_wide_td(const DemapArgs& a, const void* rec, int grid, hipStream_t st, int part) {
+hipError_t launch_mfma_wide_td(const DemapArgs& a, const void* rec, int grid, const Launch& l, int part) {
   const size_t acc = sizeof(double) * 4 * a.S * 4;
   const int64_t tbytes = table_bytes(a.M, D);
   const bool tbl = tbytes <= 40 * 1024;
@@ -666,10 +668,11 @@ hipError_t launch_mfma_wide_td(const DemapArgs& a, const void* rec, int grid, hi
   const V* r = static_cast<const V*>(rec);
   const float* x = static_cast<const float*>(a.xl);
   if (part == 0 || part == 2) {
-    if (part == 0) launch_first_tier<D, BF, false>(a, r, x, grid, st);
-    else launch_first_tier<D, BF, true>(a, r, x, grid, st);
+    if (part == 0) launch_first_tier<D, BF, false>(a, r, x, grid, l);
+    else launch_first_tier<D, BF, true>(a, r, x, grid, l);
     return hipGetLastError();
   }
+  const hipStream_t st = l.stream;
   launch_t2_collect(a, grid, st);
   const dim3 g2(t2_grid(grid));
   if (a.M == 16)

@@ -222,25 +222,23 @@ __global__ __launch_bounds__(kBlock) void demap_vec(const DemapArgs a, const T* 
 }
 
 template <typename T, int D, int G>
-hipError_t launch_vec_one(const DemapArgs& a, int grid, hipStream_t st, bool ml) {
-  const size_t shmem = sizeof(double) * (kBlock / 64) * a.S * 4;
+hipError_t launch_vec_one(const DemapArgs& a, int grid, const Launch& l, bool ml) {
+  const uint32_t shmem = (uint32_t)(sizeof(double) * (kBlock / 64) * a.S * 4);
   if (ml)
-    hipLaunchKernelGGL((demap_vec<T, D, G, true>), dim3(grid), dim3(kBlock), shmem, st, a,
-                       static_cast<const T*>(a.xl));
+    launch_kernel(l, demap_vec<T, D, G, true>, dim3(grid), dim3(kBlock), shmem, a, static_cast<const T*>(a.xl));
   else
-    hipLaunchKernelGGL((demap_vec<T, D, G, false>), dim3(grid), dim3(kBlock), shmem, st, a,
-                       static_cast<const T*>(a.xl));
+    launch_kernel(l, demap_vec<T, D, G, false>, dim3(grid), dim3(kBlock), shmem, a, static_cast<const T*>(a.xl));
   return hipGetLastError();
 }
 
 // ml: the max-log form.
 template <typename T, int D>
-hipError_t launch_vec_td(const DemapArgs& a, int grid, hipStream_t st, bool ml) {
+hipError_t launch_vec_td(const DemapArgs& a, int grid, const Launch& l, bool ml) {
   switch (a.M >= 16 ? 16 : a.M) {
-    case 2: return launch_vec_one<T, D, 2>(a, grid, st, ml);
-    case 4: return launch_vec_one<T, D, 4>(a, grid, st, ml);
-    case 8: return launch_vec_one<T, D, 8>(a, grid, st, ml);
-    default: return launch_vec_one<T, D, 16>(a, grid, st, ml);
+    case 2: return launch_vec_one<T, D, 2>(a, grid, l, ml);
+    case 4: return launch_vec_one<T, D, 4>(a, grid, l, ml);
+    case 8: return launch_vec_one<T, D, 8>(a, grid, l, ml);
+    default: return launch_vec_one<T, D, 16>(a, grid, l, ml);
   }
 }
 
