@@ -110,18 +110,17 @@ __global__ __launch_bounds__(256) void finish_kernel(const double* __restrict__ 
   // then added in block order
   constexpr int kPer = kMaxGrid / 64;
   const double* p = partials + ((int64_t)s * 4 + q) * nblocks;
-  double v[kPer];
+  double v[kPer], v2[kPer];
+  const double* p2 = t2_partials ? t2_partials + ((int64_t)s * 4 + q) * nblocks2 : nullptr;
 #pragma unroll
-  for (int i = 0; i < kPer; ++i) v[i] = lane + 64 * i < nblocks ? p[lane + 64 * i] : 0.0;
+  for (int i = 0; i < kPer; ++i) {
+    v[i] = lane + 64 * i < nblocks ? p[lane + 64 * i] : 0.0;
+    v2[i] = p2 && lane + 64 * i < nblocks2 ? p2[lane + 64 * i] : 0.0;
+  }
 #pragma unroll
   for (int i = 0; i < kPer; ++i) t += v[i];
-  if (t2_partials) {
-    const double* p2 = t2_partials + ((int64_t)s * 4 + q) * nblocks2;
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) v[i] = lane + 64 * i < nblocks2 ? p2[lane + 64 * i] : 0.0;
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) t += v[i];
-  }
+  for (int i = 0; i < kPer; ++i) t += v2[i];
   t = wave_sum(t);
   if (lane == 0) sums[q] = t;
   __syncthreads();

@@ -632,6 +632,20 @@ __global__ __launch_bounds__(256) void demap_mfma_t2(const DemapArgs a,
   const int wave = threadIdx.x >> 6;
   const int waves = blockDim.x >> 6;
   const int S = a.S;
+  // the SNR runs in the tile sequence: lane s holds run s's padded start and its
+  // sample count; T tiles in all
+  const unsigned int tot_l = lane < S ? a.t2_tot[lane] : 0u;
+  uint64_t pstart_l = 0, run = 0;
+  for (int s = 0; s < S; ++s) {
+    if (lane == s) pstart_l = run;
+    run += t2_pad(__builtin_amdgcn_readlane(tot_l, s));
+  }
+  const int64_t T = (int64_t)(run >> 5);
+  if ((int64_t)blockIdx.x * waves >= T) {
+    // no tile reaches this block: zero partials, and no tables to stage
+    for (int i = threadIdx.x; i < S * 4; i += blockDim.x) a.t2_partials[(int64_t)i * gridDim.x + blockIdx.x] = 0.0;
+    return;
+  }
   Tables<BF> tb{a.lab, xl, rec};
   if (TBL) {
     // small constellations in LDS: the tiles' operands and the exact path's
@@ -657,15 +671,6 @@ __global__ __launch_bounds__(256) void demap_mfma_t2(const DemapArgs a,
   const int64_t wstride = (int64_t)gridDim.x * waves;
   const int64_t wgid = (int64_t)blockIdx.x * waves + wave;
 
-  // the SNR runs in the tile sequence: lane s holds run s's padded start and its
-  // sample count; T tiles in all
-  const unsigned int tot_l = lane < S ? a.t2_tot[lane] : 0u;
-  uint64_t pstart_l = 0, run = 0;
-  for (int s = 0; s < S; ++s) {
-    if (lane == s) pstart_l = run;
-    run += t2_pad(__builtin_amdgcn_readlane(tot_l, s));
-  }
-  const int64_t T = (int64_t)(run >> 5);
   // wave w takes tiles w, w + waves, ...: every wave gets a share of every
   // SNR point (the high ones cost far more per sample), in increasing order
   const int64_t nmine = T > wgid ? (T - wgid + wstride - 1) / wstride : 0;

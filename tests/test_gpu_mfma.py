@@ -118,6 +118,20 @@ def test_extreme_snr_takes_exact_path(ctx):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_many_snr_points_span_launches(ctx, prec):
+    # 70 SNR points: two launches of at most 64 points each; N = 40 000 gives a
+    # first tier of 157 blocks (628 waves: three partial groups of 256 in the
+    # second tier's collection); the high points send many samples there
+    w = inputs.make("psk8x8", N=40_000, snr_db=np.linspace(-4.0, 31.0, 70))
+    st, L = _sweep(ctx, w, prec)
+    ref = oracle.sweep(w.X, w.labels, w.tx, w.z, w.snr_db)
+    _report(f"psk8x8 70 points {prec}", st, L, ref)
+    assert ctx.last_recomputed() > 0
+    assert_stats(st, ref["stats"], se_rel=2e-2)
+    assert_llr(L, ref["llr"], LLR_BAR[prec])
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_deterministic(ctx, prec):
     w = inputs.make("psk8x8", N=20_000)
     a, La = _sweep(ctx, w, prec)
