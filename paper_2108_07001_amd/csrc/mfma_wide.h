@@ -284,7 +284,10 @@ struct WideSample {
 // First tier, 64 samples per wave round. The exact-size forms of small D are
 // held to 168 registers (three waves per SIMD); what little the allocator
 // then keeps in scratch is reloaded once per SNR point, outside the sample
-// loop. MB = log2 M for the small sets
+// loop. The run-time-M forms of D <= 12 are held to 256 registers (two waves
+// per SIMD: the products then land in ordinary registers, and a second wave
+// covers the point records' L2 reads); their few spills sit outside the
+// point loop. MB = log2 M for the small sets
 // compiled at their exact size (M = 16, 32, 64: every per-bit loop and the
 // point loop are then static), 0 for any M >= 32 taken at run time. The t2
 // list and partial-sum layouts are those of demap_mfma, so the second-tier
@@ -329,7 +332,7 @@ __device__ __forceinline__ float softplus2(float x) {
 // sum can starve). Samples whose operands leave the operand range are done
 // by maxlog_direct.
 template <int D, bool BF, bool TBL, int MB, bool ML = false>
-__global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : 1) void demap_mfma_w(const DemapArgs a,
+__global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void demap_mfma_w(const DemapArgs a,
                                                     const typename MfmaOp<BF>::vec* __restrict__ rec,
                                                     const float* __restrict__ xl) {
   typedef typename MfmaOp<BF>::vec V;
