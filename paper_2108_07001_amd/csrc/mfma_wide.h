@@ -532,13 +532,20 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
         }
         float v = 0.f;
         if (live) {
+          float L[kMaxBits];
 #pragma unroll
           for (int k = 0; k < kMaxBits; ++k)
             if (k < m) {
               const float lam = side[2 * k] - side[2 * k + 1];
-              if (lout) __builtin_nontemporal_store(Real<float>::ln2() * lam, lout + k);
+              L[k] = Real<float>::ln2() * lam;
               if (tl >= 0) v += softplus2(((tl >> k) & 1) ? lam : -lam);
             }
+          // the sample's LLRs stored together, streamed past the caches
+          if (lout) {
+#pragma unroll
+            for (int k = 0; k < kMaxBits; ++k)
+              if (k < m) __builtin_nontemporal_store(L[k], lout + k);
+          }
         } else if (valid && lout) {
           for (int k = 0; k < m; ++k) lout[k] = Real<float>::nan();
         }
