@@ -227,6 +227,16 @@ __device__ __forceinline__ float diag_pick(const float16_t& acc, int j) {
   return pick(pick(v4[0], v4[1], m2), pick(v4[2], v4[3], m2), m3);
 }
 
+// An LLR of the first tier. NT: streamed past the caches (the exact-size
+// forms, whose LLR writes are a large share of the launch; the L2 then keeps
+// the inputs that the next SNR point reads again). A sample's LLRs are stored
+// back to back, so each line is still written whole.
+template <bool NT>
+__device__ __forceinline__ void store_llr(float v, float* p) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 // Raw global inputs of one sample, loaded a round ahead of use (see
 // TileInput::fetch for why the loads are unconditional and unmasked).
 template <int D>
@@ -540,11 +550,11 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
               L[k] = Real<float>::ln2() * lam;
               if (tl >= 0) v += softplus2(((tl >> k) & 1) ? lam : -lam);
             }
-          // the sample's LLRs stored together, streamed past the caches
+          // the sample's LLRs stored together
           if (lout) {
 #pragma unroll
             for (int k = 0; k < kMaxBits; ++k)
-              if (k < m) __builtin_nontemporal_store(L[k], lout + k);
+              if (k < m) store_llr<MB != 0>(L[k], lout + k);
           }
         } else if (valid && lout) {
           for (int k = 0; k < m; ++k) lout[k] = Real<float>::nan();
@@ -576,10 +586,9 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
           }
         }
         if (lout) {
-          // streamed past the caches: the LLRs are not read again here
 #pragma unroll
           for (int k = 0; k < kMaxBits; ++k)
-            if (k < m) __builtin_nontemporal_store(L[k], lout + k);
+            if (k < m) store_llr<MB != 0>(L[k], lout + k);
         }
         u = lam_tot - Real<float>::log2(Real<float>::exp2(arg_t));
       }
