@@ -184,9 +184,9 @@ class Const:
             self.ctx.lib.air_const_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # never call into the HIP runtime while the interpreter tears down
-        if sys.is_finalizing():
+        if _finalizing():
             return
         try:
             self.close()
@@ -245,8 +245,8 @@ class Context:
             self.lib.air_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()
@@ -496,8 +496,8 @@ class Pipe:
             self.h = None
             self._held.clear()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()
@@ -583,8 +583,8 @@ class Server:
             self.h = None
             self._held.clear()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()

@@ -479,14 +479,15 @@ __device__ __forceinline__ bool tier2_tile(const SampleTile<D, BF>& smp, const T
   typedef typename MfmaOp<BF>::vec V;
   constexpr int NK = SampleTile<D, BF>::NK;
   constexpr int NE = HALF ? 8 : 16;
-  const float K = Real<float>::shift(m);
   const int K64 = 1022 - m;
   const double thr64 = __builtin_ldexp(1.0, m - 1022 + 60);
+  // 2^(x - K + K64) for a product x = a_j + K (log2 units): K is an integer,
+  // so the fraction and the floor of x serve for those of a_j = x - K
+  const int dK = K64 - (int)Real<float>::shift(m);
   auto val64 = [&](float x) -> double {
-    const float ap = x - K;                         // a_j in log2 units (<= 0)
-    const float fr = __builtin_amdgcn_fractf(ap);   // ap - floor(ap), in [0, 1)
-    const int ni = (int)(ap - fr);
-    return __builtin_ldexp((double)Real<float>::exp2(fr), ni + K64);
+    const float fr = __builtin_amdgcn_fractf(x);    // x - floor(x), in [0, 1)
+    const int ni = (int)__builtin_floorf(x);
+    return __builtin_ldexp((double)Real<float>::exp2(fr), ni + dK);
   };
   TileSums<double, NE> ts;
   ts.init();

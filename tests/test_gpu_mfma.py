@@ -151,3 +151,61 @@ def test_invalid_tx(ctx):
     assert np.isnan(stats.cpu().numpy()).all()
     Lh = L.cpu().numpy()
     assert np.isnan(Lh[0, 999]).all() and np.isfinite(Lh[0, :999]).all()
+
+
+def test_call_words_start_clean(ctx):
+    # the per-call words (tx-range error, second-tier counts) are zeroed by
+    # the previous call's last kernel: counts and errors never carry over
+    w = inputs.make("psk8x8", N=20_000, snr_db=[30.0])
+    low = inputs.make("psk8x8", N=20_000, snr_db=[-2.0])
+    c = ctx.const(w.X, w.labels)
+    z = to_dev(w.z)
+
+    def run(wl, tx, sync=True):
+        st, _ = ctx.sweep(c, tx_dev(tx), z, wl.snr_db, prec="fp16x3")
+        if sync:
+            ctx.sync()
+        return st.cpu().numpy(), ctx.last_recomputed(), ctx.last_exact()
+
+    a = run(w, w.tx)
+    assert a[1] > 0
+    b = run(low, low.tx)
+    assert b[1] == 0 and b[2] == 0
+    a2 = run(w, w.tx)
+    assert a2[1:] == a[1:] and np.array_equal(a2[0], a[0])
+    bad = w.tx.astype(np.int32).copy()
+    bad[7] = 1 << 20
+    st, _ = ctx.sweep(c, tx_dev(bad), z, w.snr_db, prec="fp16x3")
+    with pytest.raises(air.AirError):
+        ctx.sync()
+    assert np.isnan(st.cpu().numpy()).all()
+    # the call after the failed one: its own words start at zero again
+    for _ in range(3):
+        b2 = run(low, low.tx)
+        assert np.array_equal(b2[0], b[0]) and b2[1] == 0 and b2[2] == 0
+        a3 = run(w, w.tx)
+        assert np.array_equal(a3[0], a[0]) and a3[1:] == a[1:]
+
+
+def test_set_stream_orders_the_workspace(ctx):
+    # switching streams waits for the work issued on the old one, which the
+    # next call's reuse of the workspace relies on
+    w = inputs.make("psk8x8", N=50_000, snr_db=np.linspace(0.0, 20.0, 9))
+    c = ctx.const(w.X, w.labels)
+    tx, z = tx_dev(w.tx), to_dev(w.z)
+    ref, _ = ctx.sweep(c, tx, z, w.snr_db, prec="fp16x3")
+    ctx.sync()
+    ref = ref.cpu().numpy()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    try:
+        for k in range(4):
+            ctx.set_stream(s1 if k % 2 == 0 else s2)
+            st, _ = ctx.sweep(c, tx, z, w.snr_db, prec="fp16x3")
+            outs.append(st)
+        ctx.sync()
+    finally:
+        ctx.set_stream(torch.cuda.default_stream())
+    torch.cuda.synchronize()
+    for st in outs:
+        assert np.array_equal(st.cpu().numpy(), ref, equal_nan=True)
