@@ -88,7 +88,8 @@ void air_destroy(air_ctx *ctx);
 
 /* Issue subsequent work on another stream of the same device. Waits first for
  * the work already issued on the current stream (the next call reuses the
- * context's workspace); returns AIR_E_DEVICE if that wait fails. */
+ * context's workspace), so the current stream must still exist; returns
+ * AIR_E_DEVICE if that wait fails. */
 air_status air_set_stream(air_ctx *ctx, void *hip_stream);
 
 /* Message describing the last failure on this context ("" if none). Owned by the context. */
