@@ -53,6 +53,18 @@ static const HdFn kHd[kMaxD + 1] = {
     launch_hd_d7, launch_hd_d8, launch_hd_d9, launch_hd_d10, launch_hd_d11, launch_hd_d12,
     launch_hd_d13, launch_hd_d14, launch_hd_d15, launch_hd_d16};
 
+// Matrix-core hard-decision launchers, one per D, defined in hd_mfma_inst.hip.
+using HdMfmaFn = hipError_t (*)(const HdArgs&, const void*, float, int, hipStream_t);
+#define AIR_DECL(D) hipError_t launch_hd_mfma_d##D(const HdArgs&, const void*, float, int, hipStream_t);
+AIR_DECL(1) AIR_DECL(2) AIR_DECL(3) AIR_DECL(4) AIR_DECL(5) AIR_DECL(6) AIR_DECL(7) AIR_DECL(8)
+AIR_DECL(9) AIR_DECL(10) AIR_DECL(11) AIR_DECL(12) AIR_DECL(13) AIR_DECL(14) AIR_DECL(15) AIR_DECL(16)
+#undef AIR_DECL
+static const HdMfmaFn kHdMfma[kMaxD + 1] = {
+    nullptr, launch_hd_mfma_d1, launch_hd_mfma_d2, launch_hd_mfma_d3, launch_hd_mfma_d4, launch_hd_mfma_d5,
+    launch_hd_mfma_d6, launch_hd_mfma_d7, launch_hd_mfma_d8, launch_hd_mfma_d9, launch_hd_mfma_d10,
+    launch_hd_mfma_d11, launch_hd_mfma_d12, launch_hd_mfma_d13, launch_hd_mfma_d14, launch_hd_mfma_d15,
+    launch_hd_mfma_d16};
+
 // Matrix-core launchers, one per (operand type, D), defined in mfma_inst_*.hip.
 using MfmaFn = hipError_t (*)(const DemapArgs&, const void*, int, const Launch&, int);
 #define AIR_DECL(tag, D) hipError_t launch_mfma_##tag##_d##D(const DemapArgs&, const void*, int, const Launch&, int);
@@ -426,7 +438,11 @@ air_status run_hd(air_ctx* ctx, const air_const* c, const float* in, const uint3
   if (e == hipSuccess && counts)
     e = hipMemsetAsync(counts, 0, sizeof(uint64_t) * 2 * (size_t)S, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "clear counters");
-  const int grid = vec_grid(N);
+  // Matrix cores for M >= 32 when the coordinates are of moderate range
+  // (max |x| in [1/16, 64]: the error bound of the product tiles holds), the
+  // vector kernel otherwise; both decide as the FP32 procedure does.
+  const bool on_mfma = c->M >= 32 && c->f16_ok && c->r2max >= 0x1p-8 && c->r2max <= 0x1p12;
+  const int grid = on_mfma ? mfma_grid(N) : vec_grid(N);
   for (int s0 = 0; s0 < S; s0 += kMaxSnrPerLaunch) {
     const int ns = (S - s0 < kMaxSnrPerLaunch) ? S - s0 : kMaxSnrPerLaunch;
     a.S = ns;
@@ -437,7 +453,8 @@ air_status run_hd(air_ctx* ctx, const air_const* c, const float* in, const uint3
     }
     a.decided = decided ? decided + (size_t)s0 * N : nullptr;
     a.counts = counts ? reinterpret_cast<unsigned long long*>(counts) + 2 * s0 : nullptr;
-    e = kHd[c->D](a, grid, ctx->stream);
+    e = on_mfma ? kHdMfma[c->D](a, c->rec_f16, (float)c->r2max, grid, ctx->stream)
+                : kHd[c->D](a, grid, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "hard-decision kernel launch");
   }
   // a tx-range error is reported by air_sync like the demapping calls'
@@ -627,6 +644,11 @@ air_status air_const_create(air_ctx* ctx, const double* X, const uint32_t* label
     c->m = bits_of(M);
     c->es = es;
     c->f16_ok = f16_ok;
+    for (int l = 0; l < M; ++l) {
+      double q = 0.0;
+      for (int d = 0; d < D; ++d) q += x64[(size_t)l * D + d] * x64[(size_t)l * D + d];
+      c->r2max = q > c->r2max ? q : c->r2max;
+    }
     hipError_t e = hipMalloc(&c->x64, sizeof(double) * M * D);
     if (e == hipSuccess) e = hipMalloc(&c->x32, sizeof(float) * M * D);
     if (e == hipSuccess) e = hipMalloc(&c->lab, sizeof(uint32_t) * M);

@@ -51,6 +51,7 @@ struct air_const {
   uint16_t* rec_f16 = nullptr;
   uint16_t* rec_bf16 = nullptr;
   bool f16_ok = false;     // coordinates and |x|^2 within the half-precision range
+  double r2max = 0.0;      // largest |x|^2
 };
 
 namespace air {

@@ -94,3 +94,52 @@ def test_hard_decide_invalid_tx(ctx):
         ctx.sync()
     assert e.value.status == air.AIR_E_RANGE
     c.close()
+
+
+def _decide_exact(ctx, X, lab, Y, tx):
+    c = ctx.const(X, lab)
+    dec, counts = ctx.hard_decide(c, to_dev(Y), tx_dev(tx))
+    ctx.sync()
+    ref = oracle.hard_decisions(X, lab, Y, tx)
+    # both sides run the FP32 procedure: identical decisions, not just ties
+    np.testing.assert_array_equal(dec.cpu().numpy().astype(np.uint32), ref["decided"])
+    np.testing.assert_array_equal(counts.cpu().numpy().astype(np.uint64), ref["counts"])
+    c.close()
+
+
+def test_hard_decide_near_ties(ctx):
+    # received points at (and within a few ulps of) midpoints of pairs of
+    # constellation points: the matrix-core path must hand these to the FP32
+    # procedure and decide exactly as it does
+    rng = np.random.default_rng(71)
+    X, lab = inputs.random_constellation(72, 64, 4)
+    a = rng.integers(0, 64, 4000)
+    b = rng.integers(0, 64, 4000)
+    mid = ((X[a] + X[b]) / 2.0).astype(np.float32)
+    jitter = rng.integers(-3, 4, mid.shape).astype(np.float32)
+    Y = np.nextafter(mid, np.where(jitter > 0, np.inf, -np.inf).astype(np.float32))
+    Y = np.where(jitter == 0, mid, Y).astype(np.float32)
+    Y = np.concatenate([mid, Y]).astype(np.float32)
+    tx = np.concatenate([a, b]).astype(np.int64)
+    _decide_exact(ctx, X, lab, Y, tx)
+
+
+@pytest.mark.parametrize("scale", [1e-2, 0.3, 8.0, 200.0])
+def test_hard_decide_coordinate_ranges(ctx, scale):
+    # largest |x| outside [1/16, 64] takes the vector kernel, inside the
+    # matrix cores; both decide as the FP32 procedure
+    X, lab = inputs.random_constellation(73, 256, 6)
+    X = X * scale
+    tx, z = inputs.random_block(74, 256, 3000, 6)
+    sigma = math.sqrt(oracle.sigma2(X, 4.0))
+    Y = (X[tx] + sigma * z.astype(np.float64)).astype(np.float32)
+    _decide_exact(ctx, X, lab, Y, tx)
+
+
+@pytest.mark.parametrize("M,D,snr", [(1024, 6, -3.0), (32, 2, 0.0), (128, 16, 10.0)])
+def test_hard_decide_low_snr_many_points(ctx, M, D, snr):
+    X, lab = inputs.random_constellation(M + 3 * D, M, D)
+    tx, z = inputs.random_block(M + 5 * D, M, 2500, D)
+    sigma = math.sqrt(oracle.sigma2(X, snr))
+    Y = (X[tx] + sigma * z.astype(np.float64)).astype(np.float32)
+    _decide_exact(ctx, X, lab, Y, tx)
