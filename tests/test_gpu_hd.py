@@ -143,3 +143,18 @@ def test_hard_decide_low_snr_many_points(ctx, M, D, snr):
     sigma = math.sqrt(oracle.sigma2(X, snr))
     Y = (X[tx] + sigma * z.astype(np.float64)).astype(np.float32)
     _decide_exact(ctx, X, lab, Y, tx)
+
+
+@pytest.mark.parametrize("N,S", [(1, 3), (33, 70), (5000, 70)])
+def test_hard_sweep_launch_edges(ctx, N, S):
+    # tiny blocks (one sample, one ragged tile pair) and more SNR points than
+    # one launch takes, on the matrix-core path (M = 64)
+    w = inputs.make("psk8x8", N=N, snr_db=np.linspace(-4.0, 30.0, S))
+    z32 = np.ascontiguousarray(w.z, dtype=np.float32)
+    c = ctx.const(w.X, w.labels)
+    counts, dec = ctx.hard_sweep(c, tx_dev(w.tx), to_dev(z32), w.snr_db, decided=True)
+    ctx.sync()
+    ref = oracle.hard_decisions_sweep(w.X, w.labels, w.tx, z32, w.snr_db, decided=True)
+    np.testing.assert_array_equal(dec.cpu().numpy().astype(np.uint32), ref["decided"])
+    np.testing.assert_array_equal(counts.cpu().numpy().astype(np.uint64), ref["counts"])
+    c.close()
