@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const double* __restrict__ 
   const int s = blockIdx.x;
   const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double t = 0.0;
-  // each lane's blocks (at most kMaxGrid / 64 = 16 per list) loaded at once,
+  // each lane's blocks (at most kMaxGrid / 64 = 24 per list) loaded at once,
   // then added in block order
   constexpr int kPer = kMaxGrid / 64;
   const double* p = partials + ((int64_t)s * 4 + q) * nblocks;

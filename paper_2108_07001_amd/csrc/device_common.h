@@ -23,7 +23,7 @@ constexpr int kMaxSnrPerLaunch = 64;
 constexpr int kMaxBits = 12;        // M <= 4096
 constexpr int kMaxD = 16;
 constexpr int kBlock = 256;         // threads per block of the vector kernels
-constexpr int kMaxGrid = 1024;      // upper bound on blocks of one demapping launch
+constexpr int kMaxGrid = 1536;      // upper bound on blocks of one demapping launch
 
 // Where a demapping kernel is launched: the stream and, for a timed launch,
 // two events that take the kernel's own start and end times from its

@@ -559,7 +559,7 @@ __host__ __device__ inline unsigned int t2_pad(unsigned int n) { return (n + 31u
 // scanned, and each thread then expands its wave's list entries (a sample
 // tile and the mask of its flagged lanes; only non-empty masks are listed)
 // into sample indices. The point's last block writes the point's total.
-constexpr int kCollectPre = 16;            // earlier 256-wave groups one block sums
+constexpr int kCollectPre = 24;            // earlier 256-wave groups one block sums
 static_assert(kMaxGrid * 4 <= 256 * kCollectPre, "a demapping launch has too many waves to collect");
 
 static __global__ __launch_bounds__(256) void t2_collect(const unsigned int* __restrict__ nitem,
