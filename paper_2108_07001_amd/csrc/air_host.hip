@@ -98,9 +98,15 @@ static int mfma_grid(int64_t N) {
   return (int)(g < kMaxGrid ? g : kMaxGrid);
 }
 
-static int vec_grid(int64_t N) {
-  int64_t g = (N + kBlock - 1) / kBlock;
-  return (int)(g < kMaxGrid ? g : kMaxGrid);
+// Grid of a vector-kernel launch: one sample per thread and round. Sets of
+// M >= 32 points take up to kMaxGrid blocks; for the small sets, whose
+// samples are cheap, the per-block reductions weigh more and 1024 blocks
+// measured faster (2-D QAM-4 buffers of 2^20 symbols: 1536 blocks, 25 %
+// slower).
+static int vec_grid(int64_t N, int M = 0) {
+  const int64_t cap = M >= 32 ? kMaxGrid : 1024;
+  const int64_t g = (N + kBlock - 1) / kBlock;
+  return (int)(g < cap ? g : cap);
 }
 
 // Fixed-order reduction of the per-block partials of one launch: block s
@@ -319,7 +325,7 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
   const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
   // matrix-core tiles hold 16 or 32 points; smaller sets run the FP32 vector kernel
   const bool mfma = (prec == AIR_FP16X3 || prec == AIR_BF16X3) && c->M >= 16;
-  const int grid = mfma ? mfma_grid(N) : vec_grid(N);
+  const int grid = mfma ? mfma_grid(N) : vec_grid(N, c->M);
   const VecFn vfn = fp64 ? kVecF64[c->D] : kVecF32[c->D];
   const MfmaFn mfn = prec == AIR_BF16X3 ? kMfmaBF16[c->D] : kMfmaF16[c->D];
   const void* rec = prec == AIR_BF16X3 ? (const void*)c->rec_bf16 : (const void*)c->rec_f16;
@@ -442,7 +448,7 @@ air_status run_hd(air_ctx* ctx, const air_const* c, const float* in, const uint3
   // (max |x| in [1/16, 64]: the error bound of the product tiles holds), the
   // vector kernel otherwise; both decide as the FP32 procedure does.
   const bool on_mfma = c->M >= 32 && c->f16_ok && c->r2max >= 0x1p-8 && c->r2max <= 0x1p12;
-  const int grid = on_mfma ? mfma_grid(N) : vec_grid(N);
+  const int grid = on_mfma ? mfma_grid(N) : vec_grid(N, c->M);
   for (int s0 = 0; s0 < S; s0 += kMaxSnrPerLaunch) {
     const int ns = (S - s0 < kMaxSnrPerLaunch) ? S - s0 : kMaxSnrPerLaunch;
     a.S = ns;
