@@ -158,3 +158,21 @@ def test_hard_sweep_launch_edges(ctx, N, S):
     np.testing.assert_array_equal(dec.cpu().numpy().astype(np.uint32), ref["decided"])
     np.testing.assert_array_equal(counts.cpu().numpy().astype(np.uint64), ref["counts"])
     c.close()
+
+
+def test_hard_decide_extreme_inputs(ctx):
+    # NaN, infinite and huge received points and one at the origin among
+    # ordinary ones: the matrix-core path (M = 64) decides them as the FP32
+    # procedure does (an undecidable point keeps label 0)
+    X, lab = inputs.random_constellation(81, 64, 4)
+    tx, z = inputs.random_block(82, 64, 250, 4)
+    Y = (X[tx] + 0.2 * z.astype(np.float64)).astype(np.float32)
+    odd = np.array([[np.nan, 0, 0, 0], [1e20, 1e20, 0, 0], [-1e19, 3, 0, 1], [1e-30, 0, 0, 0],
+                    [3e18, -2e18, 1e18, 0], [np.inf, 0, 0, 0], [0, 0, 0, 0]], dtype=np.float32)
+    Y[:len(odd)] = odd
+    c = ctx.const(X, lab)
+    dec, _ = ctx.hard_decide(c, to_dev(Y))
+    ctx.sync()
+    ref = oracle.hard_decisions(X, lab, Y)
+    np.testing.assert_array_equal(dec.cpu().numpy().astype(np.uint32), ref["decided"])
+    c.close()
