@@ -492,14 +492,21 @@ __device__ __forceinline__ bool tier2_tile(const SampleTile<D, BF>& smp, const T
   TileSums<double, NE> ts;
   ts.init();
   {
-    V A[NK];
+    // point records two tiles ahead (two register sets used in turn): one
+    // tile's work does not cover an L2 read when the records are not in LDS
+    V A0[NK], A1[NK];
     const V* rp = rec_row<BF, HALF, NK>(tb.rec, 0, j, h);
 #pragma unroll
-    for (int kk = 0; kk < NK; ++kk) A[kk] = rp[2 * kk];
-    for (int t = 0; t < NT; ++t) {
+    for (int kk = 0; kk < NK; ++kk) A0[kk] = rp[2 * kk];
+    if (NT > 1) {
+      const V* rq = rec_row<BF, HALF, NK>(tb.rec, 1, j, h);
+#pragma unroll
+      for (int kk = 0; kk < NK; ++kk) A1[kk] = rq[2 * kk];
+    }
+    auto tile = [&](V (&A)[NK], int t) {
       const float16_t acc = smp.product(A);
-      if (t + 1 < NT) {
-        const V* rq = rec_row<BF, HALF, NK>(tb.rec, t + 1, j, h);
+      if (t + 2 < NT) {
+        const V* rq = rec_row<BF, HALF, NK>(tb.rec, t + 2, j, h);
 #pragma unroll
         for (int kk = 0; kk < NK; ++kk) A[kk] = rq[2 * kk];
       }
@@ -507,6 +514,10 @@ __device__ __forceinline__ bool tier2_tile(const SampleTile<D, BF>& smp, const T
 #pragma unroll
       for (int e = 0; e < NE; ++e) ev[e] = val64(acc[e]);
       ts.add(ev, t, ntb);
+    };
+    for (int t = 0; t < NT; t += 2) {
+      tile(A0, t);
+      if (t + 1 < NT) tile(A1, t + 1);
     }
   }
   const float arg_t = has_tx ? smp.transmitted_arg(tb.rec, j, h) : 0.f;
@@ -620,7 +631,7 @@ static __global__ __launch_bounds__(256) void t2_collect(const unsigned int* __r
 // listed it; each wave sums its samples per SNR point, and the block reduces
 // its waves in a fixed order.
 template <int D, bool BF, bool HALF, bool TBL>
-__global__ __launch_bounds__(256) void demap_mfma_t2(const DemapArgs a,
+__global__ __launch_bounds__(256, D <= 12 ? 2 : 1) void demap_mfma_t2(const DemapArgs a,
                                                      const typename MfmaOp<BF>::vec* __restrict__ rec,
                                                      const float* __restrict__ xl) {
   typedef typename MfmaOp<BF>::vec V;
