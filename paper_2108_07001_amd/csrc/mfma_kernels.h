@@ -471,7 +471,7 @@ __device__ __forceinline__ void tier1_tile(const SampleTile<D, BF>& smp, const T
 // flagged finish it here, or on the exact path when even this frame starves
 // (or the sample side left the f16 range). Returns whether this lane took the
 // exact path.
-template <int D, bool BF, bool HALF>
+template <int D, bool BF, bool HALF, bool PF2 = false>
 __device__ __forceinline__ bool tier2_tile(const SampleTile<D, BF>& smp, const Tables<BF>& tb,
                                            const ExactArgs<float>& ex, bool has_tx, bool flagged,
                                            int j, int h, int m, int NT, int ntb, float* lout,
@@ -491,9 +491,28 @@ __device__ __forceinline__ bool tier2_tile(const SampleTile<D, BF>& smp, const T
   };
   TileSums<double, NE> ts;
   ts.init();
-  {
-    // point records two tiles ahead (two register sets used in turn): one
-    // tile's work does not cover an L2 read when the records are not in LDS
+  if constexpr (!PF2) {
+    V A[NK];
+    const V* rp = rec_row<BF, HALF, NK>(tb.rec, 0, j, h);
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) A[kk] = rp[2 * kk];
+    for (int t = 0; t < NT; ++t) {
+      const float16_t acc = smp.product(A);
+      if (t + 1 < NT) {
+        const V* rq = rec_row<BF, HALF, NK>(tb.rec, t + 1, j, h);
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) A[kk] = rq[2 * kk];
+      }
+      double ev[NE];
+#pragma unroll
+      for (int e = 0; e < NE; ++e) ev[e] = val64(acc[e]);
+      ts.add(ev, t, ntb);
+    }
+  } else {
+    // PF2: point records two tiles ahead (two register sets used in turn):
+    // one tile's work does not cover an L2 read when the records are not in
+    // LDS (the second tier of a launch; the serving kernels keep one, to stay
+    // within their register budget)
     V A0[NK], A1[NK];
     const V* rp = rec_row<BF, HALF, NK>(tb.rec, 0, j, h);
 #pragma unroll
@@ -734,7 +753,7 @@ __global__ __launch_bounds__(256, D <= 12 ? 2 : 1) void demap_mfma_t2(const Dema
     float u, v;
     ExactArgs<float> ex = exact_args<float>(a, s);
     ex.xl = tb.xl;
-    const bool ex_lane = tier2_tile<D, BF, HALF>(smp, tb, ex, a.tx != nullptr, flagged, j, h, m, NT, ntb,
+    const bool ex_lane = tier2_tile<D, BF, HALF, true>(smp, tb, ex, a.tx != nullptr, flagged, j, h, m, NT, ntb,
                                                  lout, u, v);
     exact += (unsigned long long)__builtin_popcountll(__ballot(ex_lane));
     if (flagged && h == 0 && smp.tl >= 0) {
