@@ -75,6 +75,14 @@ def _load():
     lib.oracle_noise_var.restype = ctypes.c_int
     lib.oracle_q_db.argtypes = [ctypes.c_double]
     lib.oracle_q_db.restype = ctypes.c_double
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.oracle_ngmi.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp]
+    lib.oracle_ngmi.restype = ctypes.c_int
+    lib.oracle_hd_rates.argtypes = [u64p, ctypes.c_int, ctypes.c_int64, ctypes.c_int, dp]
+    lib.oracle_hd_rates.restype = ctypes.c_int
+    lib.oracle_fec_net.argtypes = [dp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int,
+                                   ctypes.c_double, i32p, dp, i32p]
+    lib.oracle_fec_net.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -177,7 +185,50 @@ def noise_var(X, Y, tx):
 
 def ngmi(gmi: float, m: int) -> float:
     """Normalised GMI, 1 - (H(X) - GMI) / m with H(X) = m (reading R12)."""
-    return 1.0 - (m - gmi) / m
+    return float(ngmi_table(np.array([[np.nan, gmi, np.nan, np.nan]]), m)[0, 0])
+
+
+def ngmi_table(stats, m: int):
+    """NGMI and its standard error (S x 2) of S points of MI/GMI statistics
+    (S x 4: MI, GMI, SE_MI, SE_GMI), reading R12."""
+    st = np.ascontiguousarray(np.asarray(stats, dtype=np.float64).reshape(-1, 4))
+    out = np.empty((st.shape[0], 2))
+    rc = _load().oracle_ngmi(_ptr(st, ctypes.c_double), st.shape[0], int(m), _ptr(out, ctypes.c_double))
+    if rc != 0:
+        raise OracleError(f"oracle_ngmi failed with code {rc}")
+    return out
+
+
+def hd_rates(counts, N: int, m: int):
+    """BER, SER and Q-factor in dB (S x 3) of S points of hard-decision error
+    counts (S x 2: symbol errors, bit errors) over N symbols (readings R8, R9)."""
+    c = np.ascontiguousarray(np.asarray(counts, dtype=np.uint64).reshape(-1, 2))
+    out = np.empty((c.shape[0], 3))
+    rc = _load().oracle_hd_rates(_ptr(c, ctypes.c_uint64), c.shape[0], int(N), int(m), _ptr(out, ctypes.c_double))
+    if rc != 0:
+        raise OracleError(f"oracle_hd_rates failed with code {rc}")
+    return out
+
+
+def fec_net(ber, m: int, overhead, threshold, symbol_rate: float = 1.0):
+    """HD-FEC pass/fail (S x F), net rate (S) and the index of the code that
+    gives it (S, -1: none) for S bit error rates and F codes of the given
+    overheads (fractions) and threshold BERs (readings R15, R16)."""
+    b = np.ascontiguousarray(np.atleast_1d(np.asarray(ber, dtype=np.float64)))
+    oh = np.ascontiguousarray(np.atleast_1d(np.asarray(overhead, dtype=np.float64)))
+    th = np.ascontiguousarray(np.atleast_1d(np.asarray(threshold, dtype=np.float64)))
+    if oh.shape != th.shape:
+        raise OracleError("overhead and threshold must have the same length")
+    S, F = b.shape[0], oh.shape[0]
+    pas = np.empty((S, F), dtype=np.int32)
+    net = np.empty(S)
+    best = np.empty(S, dtype=np.int32)
+    rc = _load().oracle_fec_net(_ptr(b, ctypes.c_double), 1, S, int(m), _ptr(oh, ctypes.c_double),
+                                _ptr(th, ctypes.c_double), F, float(symbol_rate), _ptr(pas, ctypes.c_int32),
+                                _ptr(net, ctypes.c_double), _ptr(best, ctypes.c_int32))
+    if rc != 0:
+        raise OracleError(f"oracle_fec_net failed with code {rc}")
+    return {"pass": pas.astype(bool), "net": net, "best": best}
 
 
 def _evaluate(fn, X, labels, Y, noise, tx, llr, per_sample):

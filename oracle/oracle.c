@@ -547,3 +547,79 @@ int oracle_threads(void) {
   return 1;
 #endif
 }
+
+/* ---- per-SNR summaries of the rates (readings R12, R15, R16) -------------
+ *
+ * The paper evaluates each format by its bit error rate against the
+ * thresholds of two hard-decision FEC codes, of 6.7 % and 20 % overhead,
+ * and plots the net throughput of the formats that meet a threshold
+ * (Section III); it prints neither the threshold BERs nor a formula for the
+ * net rate. Readings:
+ *  R12 NGMI:  1 - (H(X) - GMI) / m with H(X) = m under the uniform prior,
+ *             i.e. GMI / m; its standard error is SE_GMI / m.
+ *  R15 HD-FEC: a code of overhead OH (fraction: 0.067, 0.2) and threshold
+ *             BER th is met when BER <= th (a NaN BER meets nothing).
+ *  R16 net rate: a code of overhead OH carries m / (1 + OH) information
+ *             bits per symbol (code rate 1 / (1 + OH)); the net rate is the
+ *             largest such value over the codes that are met, times the
+ *             symbol rate, and 0 when none is met. Ties keep the code listed
+ *             first.
+ */
+
+/* NGMI and its SE for S points of MI/GMI statistics (S x 4: MI, GMI, SE_MI,
+ * SE_GMI); out is S x 2. */
+int oracle_ngmi(const double *stats, int S, int m, double *out) {
+  if (!stats || !out || S < 1 || m < 1) return ORACLE_E_INVAL;
+  for (int s = 0; s < S; ++s) {
+    const double gmi = stats[4 * s + 1], se = stats[4 * s + 3];
+    const double hx = (double)m;                 /* entropy of the uniform input, bits */
+    out[2 * s] = 1.0 - (hx - gmi) / (double)m;
+    out[2 * s + 1] = se / (double)m;
+  }
+  return ORACLE_OK;
+}
+
+/* BER, SER and Q-factor (dB) of S points of hard-decision error counts
+ * (S x 2: symbol errors, bit errors) over N symbols of m bits (R8, R9);
+ * out is S x 3. */
+int oracle_hd_rates(const uint64_t *counts, int S, int64_t N, int m, double *out) {
+  if (!counts || !out || S < 1 || N < 1 || m < 1) return ORACLE_E_INVAL;
+  for (int s = 0; s < S; ++s) {
+    const double ser = (double)counts[2 * s] / (double)N;
+    const double ber = (double)counts[2 * s + 1] / ((double)N * (double)m);
+    out[3 * s] = ber;
+    out[3 * s + 1] = ser;
+    out[3 * s + 2] = oracle_q_db(ber);
+  }
+  return ORACLE_OK;
+}
+
+/* HD-FEC pass/fail and net rate for S points of BERs (ber[s * stride]) and F
+ * codes (overhead[f], threshold[f]) (R15, R16).
+ *  pass: S x F (1 met, 0 not), or NULL
+ *  net:  S net rates (symbol_rate x bits per symbol), or NULL
+ *  best: S indices of the code that gives the net rate (-1: none), or NULL */
+int oracle_fec_net(const double *ber, int64_t stride, int S, int m, const double *overhead,
+                   const double *threshold, int F, double symbol_rate, int32_t *pass, double *net,
+                   int32_t *best) {
+  if (!ber || stride < 1 || S < 1 || m < 1 || !overhead || !threshold || F < 1) return ORACLE_E_INVAL;
+  for (int f = 0; f < F; ++f)
+    if (!(overhead[f] >= 0.0) || !(threshold[f] >= 0.0)) return ORACLE_E_INVAL;
+  for (int s = 0; s < S; ++s) {
+    const double b = ber[(int64_t)s * stride];
+    double top = 0.0;
+    int arg = -1;
+    for (int f = 0; f < F; ++f) {
+      const int ok = b <= threshold[f];          /* false for a NaN BER */
+      if (pass) pass[(int64_t)s * F + f] = ok;
+      const double rate = (double)m / (1.0 + overhead[f]);
+      if (ok && rate > top) {
+        top = rate;
+        arg = f;
+      }
+    }
+    if (net) net[s] = symbol_rate * top;
+    if (best) best[s] = arg;
+  }
+  return ORACLE_OK;
+}

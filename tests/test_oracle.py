@@ -540,3 +540,79 @@ def test_maxlog_high_snr_limit_and_sweep():
     Y = w.X[w.tx] + math.sqrt(oracle.sigma2(w.X, 40.0)) * w.z.astype(np.float64)
     e = oracle.evaluate_maxlog(w.X, w.labels, Y, 40.0, tx=w.tx)
     np.testing.assert_array_equal(r["llr"][0], e["llr"])
+
+
+# ---- per-SNR summaries: NGMI table, BER/SER/Q, HD-FEC and net rate (R12, R15, R16) ----
+
+def test_ngmi_table_of_pmqpsk_is_the_bpsk_capacity():
+    """PM-QPSK's GMI is 4 C_BPSK(snr) (the likelihood factorises per dimension),
+    so its NGMI = GMI / 4 is the BPSK capacity itself; Monte Carlo within 4 SE.
+    The SE column is SE_GMI / m."""
+    w = inputs.make("pmqpsk", N=20000)
+    snr = [0.0, 3.0, 6.0]
+    r = oracle.sweep(w.X, w.labels, w.tx, w.z, snr, llr=False)
+    t = oracle.ngmi_table(r["stats"], 4)
+    for s, row, st in zip(snr, t, r["stats"]):
+        c = truths.c_bpsk(10 ** (s / 10))
+        assert abs(row[0] - c) <= 4 * row[1], (s, row, c)
+        assert row[1] == pytest.approx(st[3] / 4, rel=1e-15)
+    hi = oracle.sweep(w.X, w.labels, w.tx, w.z, [40.0], llr=False)
+    assert oracle.ngmi_table(hi["stats"], 4)[0, 0] == pytest.approx(1.0, abs=1e-12)
+
+
+def test_hd_rates_of_gray_qpsk_against_erfc():
+    """BER and SER columns against the Gray-QPSK closed forms (each bit is BPSK
+    with amplitude^2 / sigma^2 = snr), Q against scipy's erfcinv of 2 BER."""
+    from scipy.special import erfcinv
+    X, labels = _gray_qpsk()
+    N = 200_000
+    tx, z = inputs.random_block(98, 4, N, 2)
+    snr_db = [1.0, 5.0, 8.0]
+    counts = oracle.hard_decisions_sweep(X, labels, tx, z, snr_db)["counts"]
+    rates = oracle.hd_rates(counts, N, 2)
+    for s, (ber, ser, q) in zip(snr_db, rates):
+        p = 0.5 * math.erfc(math.sqrt(10 ** (s / 10) / 2.0))
+        assert abs(ber - p) <= 5 * math.sqrt(p * (1 - p) / (2 * N))
+        ps = 1 - (1 - p) ** 2
+        assert abs(ser - ps) <= 5 * math.sqrt(ps * (1 - ps) / N)
+        assert q == pytest.approx(20 * math.log10(math.sqrt(2.0) * erfcinv(2 * ber)), abs=1e-9)
+    none = oracle.hd_rates([[0, 0]], 10, 2)[0]
+    assert none[0] == 0.0 and none[1] == 0.0 and math.isnan(none[2])
+
+
+def test_fec_net_rate_of_gray_qpsk_sweep():
+    """Across an SNR sweep of Gray QPSK the net rate steps from 0 to
+    2 / (1 + OH) of the code whose threshold the BER meets; the points well
+    away from a threshold crossing follow the erfc closed form."""
+    X, labels = _gray_qpsk()
+    N = 100_000
+    tx, z = inputs.random_block(99, 4, N, 2)
+    snr_db = np.arange(0.0, 12.5, 0.5)
+    counts = oracle.hard_decisions_sweep(X, labels, tx, z, snr_db)["counts"]
+    ber = oracle.hd_rates(counts, N, 2)[:, 0]
+    oh, th = [0.067, 0.2], [3.8e-3, 2.0e-2]
+    out = oracle.fec_net(ber, 2, oh, th, symbol_rate=1e9)
+    for s, b, net, best, pas in zip(snr_db, ber, out["net"], out["best"], out["pass"]):
+        p = 0.5 * math.erfc(math.sqrt(10 ** (s / 10) / 2.0))
+        for f in range(2):
+            if abs(p - th[f]) > 6 * math.sqrt(p * (1 - p) / (2 * N)):
+                assert pas[f] == (p < th[f]), (s, p, th[f])
+        want = max([2.0 / (1.0 + oh[f]) for f in range(2) if b <= th[f]], default=0.0)
+        assert net == pytest.approx(1e9 * want, rel=1e-15)
+        assert (best < 0) == (want == 0.0)
+    # non-decreasing in SNR (the BER of one sample set falls with SNR), and
+    # the lowest-overhead code once every code is met
+    assert np.all(np.diff(out["net"]) >= 0)
+    assert out["net"][-1] == pytest.approx(1e9 * 2 / 1.067) and out["best"][-1] == 0
+
+
+def test_fec_net_edge_cases():
+    r = oracle.fec_net([0.0, 0.02, 0.0200001, float("nan")], 6, [0.067, 0.2], [3.8e-3, 2.0e-2])
+    assert r["pass"].tolist() == [[True, True], [False, True], [False, False], [False, False]]
+    assert r["net"][0] == pytest.approx(6 / 1.067) and r["net"][1] == pytest.approx(5.0)
+    assert r["net"][2] == 0.0 and r["net"][3] == 0.0
+    assert r["best"].tolist() == [0, 1, -1, -1]
+    # equal rates: the code listed first
+    assert oracle.fec_net([1e-3], 4, [0.2, 0.2], [1e-2, 1e-2])["best"][0] == 0
+    with pytest.raises(oracle.OracleError):
+        oracle.fec_net([1e-3], 4, [-0.1], [1e-2])
