@@ -201,6 +201,29 @@ air_status air_mi_gmi_aux(air_ctx *ctx, const air_const *c, const void *Y_dev,
                           const uint32_t *tx_dev, int64_t N, double sigma2_aux, air_prec prec,
                           double *stats_dev, void *llr_dev);
 
+/* The chain a receiver runs on measured data, in one call: the isotropic
+ * noise-variance estimate of air_noise_var, then air_mi_gmi_aux with that
+ * variance, then the NGMI of air_ngmi. Synchronises (the estimate is read
+ * back to form the metric).
+ *  var_host:   D + 1 doubles (host) receiving the estimates as air_noise_var
+ *              writes them, or NULL.
+ *  rates_host: 7 doubles (host): sigma2 (the isotropic estimate), MI, GMI,
+ *              SE_MI, SE_GMI, NGMI, SE_NGMI.
+ * AIR_E_RANGE, with NaN rates, if a tx index is >= M or the estimate is zero
+ * (received points equal to the transmitted ones). */
+air_status air_aux_rates(air_ctx *ctx, const air_const *c, const void *Y_dev,
+                         const uint32_t *tx_dev, int64_t N, air_prec prec, double *var_host,
+                         double *rates_host);
+
+/* Normalised GMI of S points of statistics, host arithmetic on host arrays:
+ * NGMI = 1 - (H(X) - GMI) / m with H(X) = m bits under the uniform prior over
+ * M = 2^m points (so GMI / m), and its standard error SE_GMI / m.
+ *  stats_host: S x 4 doubles as air_mi_gmi / air_sweep write them (MI, GMI,
+ *              SE_MI, SE_GMI), copied to the host by the caller.
+ *  ngmi_host:  S x 2 doubles: NGMI, SE_NGMI.
+ * AIR_E_INVAL for null pointers, S < 1 or m < 1. */
+air_status air_ngmi(const double *stats_host, int S, int m, double *ngmi_host);
+
 /* ---------------------------------------------------------------------------
  * Max-log demapping, the usual receiver simplification of soft demapping:
  * each bit side's log-sum-exp is replaced by its largest term, so that
@@ -254,6 +277,44 @@ air_status air_hard_sweep(air_ctx *ctx, const air_const *c, const uint32_t *tx_d
  * Gaussian-tail conversion (the paper quotes Q estimated from the BER without
  * printing the conversion). NaN unless 0 < BER < 0.5. */
 double air_q_factor_db(double ber);
+
+/* BER, SER and Q-factor of S points of hard-decision error counts, host
+ * arithmetic on host arrays (the paper evaluates every format by its
+ * Q-factor estimated from the BER; Sections II and III).
+ *  counts_host: S x 2 uint64 as air_hard_sweep writes them (symbol errors,
+ *               bit errors), copied to the host by the caller.
+ *  N, m:        symbols per SNR point and bits per symbol.
+ *  rates_host:  S x 3 doubles: BER = bit errors / (N m), SER = symbol
+ *               errors / N, Q_dB = air_q_factor_db(BER) (NaN unless
+ *               0 < BER < 0.5).
+ * AIR_E_INVAL for null pointers, S < 1, N < 1 or m < 1. */
+air_status air_hd_rates(const uint64_t *counts_host, int S, int64_t N, int m, double *rates_host);
+
+/* Hard-decision FEC pass/fail and net rate of S points of BERs against F
+ * codes, host arithmetic on host arrays. The paper compares each format's
+ * BER with the thresholds of a 6.7 % and a 20 % overhead hard-decision FEC
+ * and plots the net throughput of the formats that meet one (Section III);
+ * it prints neither the threshold BERs nor the net-rate formula, so the
+ * codes are the caller's and the readings are:
+ *  - a code of overhead OH (a fraction, e.g. 0.067) and threshold BER th is
+ *    met when BER <= th (a NaN BER meets none);
+ *  - the code carries m / (1 + OH) information bits per symbol (code rate
+ *    1 / (1 + OH));
+ *  - the net rate is the largest of those over the codes met, times
+ *    symbol_rate (symbols per second, or 1 for bits per symbol), and 0 when
+ *    no code is met; ties keep the code listed first.
+ *  ber_host:   BER of point s at ber_host[s * stride] (stride 3 reads the BER
+ *              column of air_hd_rates' output).
+ *  overhead, threshold: F doubles each (>= 0, overhead finite).
+ *  pass_host:  S x F int32 (1 met, 0 not), or NULL.
+ *  net_host:   S doubles, or NULL.
+ *  code_host:  S int32: the code that gives the net rate, -1 for none; or NULL.
+ * AIR_E_INVAL for null inputs, stride < 1, S < 1, m < 1, F < 1, a negative
+ * or non-finite overhead, a negative or NaN threshold, or a negative or
+ * non-finite symbol_rate. */
+air_status air_fec_net(const double *ber_host, int64_t stride, int S, int m, const double *overhead,
+                       const double *threshold, int F, double symbol_rate, int32_t *pass_host,
+                       double *net_host, int32_t *code_host);
 
 /* ---------------------------------------------------------------------------
  * Per-buffer streaming from host memory. The paper's receiver moves buffers
@@ -382,8 +443,10 @@ air_status air_server_query(air_server *s, air_server_info *info);
 const char *air_server_last_error(const air_server *s);
 
 /* Finish every submitted job, stop the worker and release the arena and
- * streams. Results not yet polled are discarded. NULL is ignored. */
-void air_server_destroy(air_server *s);
+ * streams. Results not yet polled are discarded. Returns AIR_E_DEVICE if the
+ * server had failed on the device (its unfinished jobs are then dropped),
+ * else AIR_OK; AIR_E_INVAL for NULL. */
+air_status air_server_destroy(air_server *s);
 
 #ifdef __cplusplus
 }

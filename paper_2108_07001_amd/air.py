@@ -141,7 +141,15 @@ def load() -> ctypes.CDLL:
     lib.air_server_last_error.argtypes = [vp]
     lib.air_server_last_error.restype = ctypes.c_char_p
     lib.air_server_destroy.argtypes = [vp]
-    lib.air_server_destroy.restype = None
+    lib.air_server_destroy.restype = ci
+    lib.air_aux_rates.argtypes = [vp, vp, vp, vp, i64, ci, vp, vp]
+    lib.air_aux_rates.restype = ci
+    lib.air_ngmi.argtypes = [vp, ci, ci, vp]
+    lib.air_ngmi.restype = ci
+    lib.air_hd_rates.argtypes = [vp, ci, i64, ci, vp]
+    lib.air_hd_rates.restype = ci
+    lib.air_fec_net.argtypes = [vp, i64, ci, ci, vp, vp, ci, dbl, vp, vp, vp]
+    lib.air_fec_net.restype = ci
     _lib = lib
     return lib
 
@@ -338,17 +346,21 @@ class Context:
         return stats, L
 
     def aux_rates(self, c: Const, Y: torch.Tensor, tx: torch.Tensor, prec: str = "fp32"):
-        """Estimate the isotropic noise variance from (Y, tx), then the rates of
-        the receiver that demaps with it. Synchronises once (the estimate is
-        read back to form the metric). Returns a dict with sigma2, the
-        per-dimension variances, MI, GMI, their SEs and NGMI."""
-        var_dev = self.noise_var(c, Y, tx, prec)
-        self.sync()                      # the library's stream, then a plain copy
-        var = var_dev.cpu().numpy()
-        stats, _ = self.mi_gmi_aux(c, Y, tx, float(var[-1]), prec)
-        st = stats.cpu().numpy()
-        return {"sigma2": float(var[-1]), "var": var[:-1], "mi": float(st[0]), "gmi": float(st[1]),
-                "se_mi": float(st[2]), "se_gmi": float(st[3]), "ngmi": ngmi(float(st[1]), c.m)}
+        """air_aux_rates: the isotropic noise-variance estimate from (Y, tx), then
+        the rates of the receiver that demaps with it and their NGMI (synchronises).
+        Returns a dict with sigma2, the per-dimension variances, MI, GMI, their
+        SEs, NGMI and its SE."""
+        self._check_block(Y, c, prec, "Y")
+        N = Y.shape[0]
+        self._check_tx(tx, N)
+        var = np.empty(c.D + 1)
+        rates = np.empty(7)
+        self.check(self.lib.air_aux_rates(self.h, c.h, _ptr(Y), _ptr(tx), N, PREC[prec],
+                                          var.ctypes.data, rates.ctypes.data))
+        keys = ["sigma2", "mi", "gmi", "se_mi", "se_gmi", "ngmi", "se_ngmi"]
+        out = {k: float(v) for k, v in zip(keys, rates)}
+        out["var"] = var[:-1]
+        return out
 
     def hard_decide(self, c: Const, Y: torch.Tensor, tx: Optional[torch.Tensor] = None,
                     decided: bool = True):
@@ -606,9 +618,49 @@ def air_const_create(ctx: Context, X, labels) -> Const:
     return ctx.const(X, labels)
 
 
+def _check_host(st: int, what: str):
+    if st != AIR_OK:
+        raise AirError(st, what)
+
+
+def ngmi_table(stats, m: int) -> np.ndarray:
+    """air_ngmi: NGMI and its SE (S x 2) of S points of statistics (S x 4)."""
+    st = np.ascontiguousarray(np.asarray(stats, dtype=np.float64).reshape(-1, 4))
+    out = np.empty((st.shape[0], 2))
+    _check_host(load().air_ngmi(st.ctypes.data, st.shape[0], int(m), out.ctypes.data), "air_ngmi")
+    return out
+
+
 def ngmi(gmi: float, m: int) -> float:
-    """Normalised GMI, 1 - (H(X) - GMI) / m with H(X) = m (uniform prior)."""
-    return 1.0 - (m - gmi) / m
+    """NGMI of one GMI value (air_ngmi)."""
+    return float(ngmi_table([[np.nan, gmi, np.nan, np.nan]], m)[0, 0])
+
+
+def hd_rates(counts, N: int, m: int) -> np.ndarray:
+    """air_hd_rates: BER, SER, Q_dB (S x 3) of S points of error counts (S x 2)."""
+    c = np.ascontiguousarray(np.asarray(counts, dtype=np.uint64).reshape(-1, 2))
+    out = np.empty((c.shape[0], 3))
+    _check_host(load().air_hd_rates(c.ctypes.data, c.shape[0], int(N), int(m), out.ctypes.data),
+                "air_hd_rates")
+    return out
+
+
+def fec_net(ber, m: int, overhead, threshold, symbol_rate: float = 1.0) -> dict:
+    """air_fec_net: HD-FEC pass/fail (S x F), net rate (S) and the code giving it
+    (S, -1 for none) for S BERs and F codes (overheads and threshold BERs)."""
+    b = np.ascontiguousarray(np.atleast_1d(np.asarray(ber, dtype=np.float64)))
+    oh = np.ascontiguousarray(np.atleast_1d(np.asarray(overhead, dtype=np.float64)))
+    th = np.ascontiguousarray(np.atleast_1d(np.asarray(threshold, dtype=np.float64)))
+    if oh.shape != th.shape:
+        raise AirError(AIR_E_INVAL, "overhead and threshold must have the same length")
+    S, F = b.shape[0], oh.shape[0]
+    pas = np.empty((S, F), dtype=np.int32)
+    net = np.empty(S)
+    code = np.empty(S, dtype=np.int32)
+    _check_host(load().air_fec_net(b.ctypes.data, 1, S, int(m), oh.ctypes.data, th.ctypes.data, F,
+                                   float(symbol_rate), pas.ctypes.data, net.ctypes.data, code.ctypes.data),
+                "air_fec_net")
+    return {"pass": pas.astype(bool), "net": net, "code": code}
 
 
 def air_llr(ctx: Context, c: Const, Y, snr_db, prec="fp32", out=None):

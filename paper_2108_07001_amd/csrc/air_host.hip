@@ -528,6 +528,7 @@ air_status air_create(air_ctx** out, int device, void* hip_stream) {
     if (e == hipSuccess) e = hipMalloc(&ctx->t2_tot, sizeof(unsigned int) * kMaxSnrPerLaunch);
     if (e == hipSuccess) e = hipMalloc(&ctx->calls, 2 * sizeof(CallWords));
     if (e == hipSuccess) e = hipMalloc(&ctx->sticky, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&ctx->small, sizeof(double) * kSmallDoubles);
     if (e == hipSuccess) e = hipMemset(ctx->calls, 0, 2 * sizeof(CallWords));
     ctx->call = ctx->calls;
     if (e == hipSuccess) e = hipMemset(ctx->sticky, 0, sizeof(int));
@@ -553,6 +554,7 @@ void air_destroy(air_ctx* ctx) {
   free_t2(ctx);
   (void)hipFree(ctx->t2_partials);
   (void)hipFree(ctx->t2_tot);
+  (void)hipFree(ctx->small);
   for (hipEvent_t ev : ctx->ev) (void)hipEventDestroy(ev);
   delete ctx;
 }
@@ -731,6 +733,48 @@ air_status air_mi_gmi_aux(air_ctx* ctx, const air_const* c, const void* Y_dev, c
   if (ctx && (!tx_dev || !stats_dev)) return fail(ctx, AIR_E_INVAL, "tx_dev and stats_dev must not be null");
   try {
     return run(ctx, c, Y_dev, tx_dev, N, &sigma2_aux, 1, 0, prec, stats_dev, llr_dev, true);
+  } catch (...) {
+    return fail(ctx, AIR_E_NOMEM, "host allocation failed");
+  }
+}
+
+air_status air_aux_rates(air_ctx* ctx, const air_const* c, const void* Y_dev, const uint32_t* tx_dev,
+                         int64_t N, air_prec prec, double* var_host, double* rates_host) {
+  if (ctx && !rates_host) return fail(ctx, AIR_E_INVAL, "rates_host is null");
+  try {
+    if (!ctx) return AIR_E_INVAL;
+    if (!c || c->ctx != ctx) return fail(ctx, AIR_E_INVAL, "constellation is null or from another context");
+    static_assert(kMaxD + 1 + 4 <= kSmallDoubles, "small device buffer too small");
+    double* var_dev = ctx->small;
+    double* stats_dev = ctx->small + (kMaxD + 1);
+    air_status st = run_noise_var(ctx, c, Y_dev, tx_dev, N, prec, var_dev);
+    if (st != AIR_OK) return st;
+    DeviceGuard g(ctx->device);
+    double var[kMaxD + 1];
+    // the estimate is needed on the host to form the metric's scale
+    hipError_t e = hipMemcpyAsync(var, var_dev, sizeof(double) * (c->D + 1), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "read the noise estimate");
+    if (var_host)
+      for (int d = 0; d <= c->D; ++d) var_host[d] = var[d];
+    const double s2 = var[c->D];
+    if (!(s2 > 0.0) || !std::isfinite(s2)) {
+      for (int i = 0; i < 7; ++i) rates_host[i] = std::nan("");
+      rates_host[0] = s2;
+      const air_status se = air_sync(ctx);   // reports a tx-range error
+      return se != AIR_OK ? se : fail(ctx, AIR_E_RANGE, "noise estimate is zero or not finite");
+    }
+    st = run(ctx, c, Y_dev, tx_dev, N, &s2, 1, 0, prec, stats_dev, nullptr, true);
+    if (st != AIR_OK) return st;
+    double stats[4];
+    e = hipMemcpyAsync(stats, stats_dev, sizeof(stats), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "read the rates");
+    rates_host[0] = s2;
+    for (int i = 0; i < 4; ++i) rates_host[1 + i] = stats[i];
+    st = air_ngmi(stats, 1, c->m, rates_host + 5);
+    if (st != AIR_OK) return fail(ctx, st, "NGMI");
+    return air_sync(ctx);
   } catch (...) {
     return fail(ctx, AIR_E_NOMEM, "host allocation failed");
   }

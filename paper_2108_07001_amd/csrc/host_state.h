@@ -11,6 +11,8 @@
 #include <string>
 #include <vector>
 
+constexpr int kSmallDoubles = 32;
+
 struct air_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -32,6 +34,9 @@ struct air_ctx {
   unsigned int* t2_nitem = nullptr;
   uint32_t* t2_items = nullptr;
   unsigned int* t2_tot = nullptr; // kMaxSnrPerLaunch
+  // device results of the chained calls (air_aux_rates): the noise-variance
+  // estimates (D + 1) and one SNR point's statistics (4)
+  double* small = nullptr;       // kSmallDoubles
   // optional timing of the demapping kernels (air_set_timing)
   bool timing = false;
   std::vector<hipEvent_t> ev;    // start/stop pairs recorded since the last read

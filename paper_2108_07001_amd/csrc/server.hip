@@ -629,10 +629,11 @@ air_status air_server_query(air_server* s, air_server_info* info) {
 
 const char* air_server_last_error(const air_server* s) { return s ? s->err.c_str() : "null server"; }
 
-void air_server_destroy(air_server* s) {
-  if (!s) return;
-  (void)air_server_drain(s, -1);
+air_status air_server_destroy(air_server* s) {
+  if (!s) return AIR_E_INVAL;
+  const air_status st = air_server_drain(s, -1);
   destroy_server(s);
+  return st;
 }
 
 }  // extern "C"

@@ -89,6 +89,23 @@ def test_aux_rates_end_to_end(ctx):
     ref = oracle.evaluate_aux(w.X, w.labels, Y.astype(np.float64), ref_var[-1], tx=w.tx, llr=False)
     assert abs(r["mi"] - ref["stats"][0]) <= 1e-4 and abs(r["gmi"] - ref["stats"][1]) <= 1e-4
     assert r["ngmi"] == pytest.approx(oracle.ngmi(ref["stats"][1], 6), abs=2e-5)
+    np.testing.assert_allclose(r["var"], ref_var[:-1], rtol=1e-12)
+    assert r["se_ngmi"] == pytest.approx(r["se_gmi"] / 6, rel=1e-15)
+    assert abs(r["se_gmi"] - ref["stats"][3]) <= 1e-2 * ref["stats"][3] + 1e-6
+    c.close()
+
+
+def test_aux_rates_range_error(ctx):
+    X, lab, tx, Y, s2 = _block(92, 16, 2, 100, 5.0)
+    c = ctx.const(X, lab)
+    badtx = tx.astype(np.int64).copy()
+    badtx[7] = 99
+    with pytest.raises(air.AirError) as e:
+        ctx.aux_rates(c, to_dev(Y), tx_dev(badtx), "fp32")
+    assert e.value.status == air.AIR_E_RANGE
+    # the context stays usable
+    r = ctx.aux_rates(c, to_dev(Y), tx_dev(tx), "fp32")
+    assert r["sigma2"] == pytest.approx(oracle.noise_var(X, Y.astype(np.float64), tx)[-1], rel=1e-12)
     c.close()
 
 
