@@ -217,29 +217,61 @@ double from_bf16_bits(uint16_t b) {
   return (double)f;
 }
 
-// Point side of the matrix-core K slots for one point x (length D), in the
-// order [x_hi | x_lo | x_hi | q_hi, q_lo, q_hi | 1 | 0...], q = |x|^2, as
-// operand bits; hi = round(v), lo = round(v - hi).
+// Point side of the matrix-core K slots for one point x (length D), as
+// operand bits, q = |x|^2, every part rounded to nearest even:
+//  half precision: [x_hi | x_lo | x_hi | q_hi, q_lo, q_hi | 1 | 0...],
+//    hi = round(v), lo = round(v - hi);
+//  bfloat16: [x_hi | x_mid | x_lo | x_hi | x_mid | x_hi |
+//             q_hi, q_mid, q_lo, q_hi, q_mid, q_hi | 1 | 0...],
+//    hi = round(v), mid = round(v - hi), lo = round(v - hi - mid).
+// The 1 multiplies the sample side's per-sample shift.
 void point_record(const double* x, int D, bool bf, uint16_t* out) {
-  const int kp = 16 * mfma_nk(D);
+  const int kp = 16 * mfma_nk(D, bf);
   auto cv = [bf](double v) { return bf ? to_bf16_bits(v) : to_f16_bits(v); };
   auto back = [bf](uint16_t b) { return bf ? from_bf16_bits(b) : from_f16_bits(b); };
   for (int k = 0; k < kp; ++k) out[k] = 0;
   double q = 0.0;
-  for (int d = 0; d < D; ++d) {
-    const uint16_t hi = cv(x[d]);
-    const uint16_t lo = cv(x[d] - back(hi));
-    out[d] = hi;
-    out[D + d] = lo;
-    out[2 * D + d] = hi;
-    q += x[d] * x[d];
+  for (int d = 0; d < D; ++d) q += x[d] * x[d];
+  if (!bf) {
+    for (int d = 0; d < D; ++d) {
+      const uint16_t hi = cv(x[d]);
+      const uint16_t lo = cv(x[d] - back(hi));
+      out[d] = hi;
+      out[D + d] = lo;
+      out[2 * D + d] = hi;
+    }
+    const uint16_t qh = cv(q);
+    const uint16_t ql = cv(q - back(qh));
+    out[3 * D] = qh;
+    out[3 * D + 1] = ql;
+    out[3 * D + 2] = qh;
+  } else {
+    auto split3 = [&](double v, uint16_t& hi, uint16_t& mid, uint16_t& lo) {
+      hi = cv(v);
+      const double r = v - back(hi);
+      mid = cv(r);
+      lo = cv(r - back(mid));
+    };
+    for (int d = 0; d < D; ++d) {
+      uint16_t hi, mid, lo;
+      split3(x[d], hi, mid, lo);
+      out[d] = hi;
+      out[D + d] = mid;
+      out[2 * D + d] = lo;
+      out[3 * D + d] = hi;
+      out[4 * D + d] = mid;
+      out[5 * D + d] = hi;
+    }
+    uint16_t qh, qm, ql;
+    split3(q, qh, qm, ql);
+    out[6 * D] = qh;
+    out[6 * D + 1] = qm;
+    out[6 * D + 2] = ql;
+    out[6 * D + 3] = qh;
+    out[6 * D + 4] = qm;
+    out[6 * D + 5] = qh;
   }
-  const uint16_t qh = cv(q);
-  const uint16_t ql = cv(q - back(qh));
-  out[3 * D] = qh;
-  out[3 * D + 1] = ql;
-  out[3 * D + 2] = qh;
-  out[3 * D + 3] = cv(1.0);   // multiplies the sample side's per-sample shift
+  out[shift_slot(D, bf)] = cv(1.0);
 }
 
 // Per-SNR scalars of one launch.
@@ -628,8 +660,9 @@ air_status air_const_create(air_ctx* ctx, const double* X, const uint32_t* label
     }
     es /= (double)M;
     if (!(es > 0.0)) return fail(ctx, AIR_E_INVAL, "constellation has zero energy");
-    const int kp = 16 * mfma_nk(D);
-    std::vector<uint16_t> r16((size_t)M * kp), rbf((size_t)M * kp);
+    const int kp = 16 * mfma_nk(D, false);
+    const int kpb = 16 * mfma_nk(D, true);
+    std::vector<uint16_t> r16((size_t)M * kp), rbf((size_t)M * kpb);
     bool f16_ok = true;
     for (int l = 0; l < M; ++l) {
       double q = 0.0;
@@ -640,7 +673,7 @@ air_status air_const_create(air_ctx* ctx, const double* X, const uint32_t* label
       }
       f16_ok &= q < 60000.0;
       point_record(&x64[(size_t)l * D], D, false, &r16[(size_t)l * kp]);
-      point_record(&x64[(size_t)l * D], D, true, &rbf[(size_t)l * kp]);
+      point_record(&x64[(size_t)l * D], D, true, &rbf[(size_t)l * kpb]);
     }
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, AIR_E_DEVICE, "cannot select the context's device");
@@ -662,9 +695,9 @@ air_status air_const_create(air_ctx* ctx, const double* X, const uint32_t* label
     if (e == hipSuccess) e = hipMalloc(&c->lab, sizeof(uint32_t) * M);
     if (e == hipSuccess) e = hipMalloc(&c->pos, sizeof(uint32_t) * M);
     if (e == hipSuccess) e = hipMalloc(&c->rec_f16, sizeof(uint16_t) * M * kp);
-    if (e == hipSuccess) e = hipMalloc(&c->rec_bf16, sizeof(uint16_t) * M * kp);
+    if (e == hipSuccess) e = hipMalloc(&c->rec_bf16, sizeof(uint16_t) * M * kpb);
     if (e == hipSuccess) e = hipMemcpy(c->rec_f16, r16.data(), sizeof(uint16_t) * M * kp, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(c->rec_bf16, rbf.data(), sizeof(uint16_t) * M * kp, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->rec_bf16, rbf.data(), sizeof(uint16_t) * M * kpb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->x64, x64.data(), sizeof(double) * M * D, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->x32, x32.data(), sizeof(float) * M * D, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->lab, labels, sizeof(uint32_t) * M, hipMemcpyHostToDevice);

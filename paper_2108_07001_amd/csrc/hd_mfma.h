@@ -43,7 +43,7 @@ __device__ __forceinline__ void hd_take(float d, int l, float& bd, int& bl) {
 
 // Bytes of the block-local copies of the coordinates and point records.
 __host__ __device__ constexpr int64_t hd_table_bytes(int M, int D) {
-  return (int64_t)M * D * 4 + 16 + (int64_t)M * mfma_nk(D) * 32;
+  return (int64_t)M * D * 4 + 16 + (int64_t)M * mfma_nk(D, false) * 32;
 }
 
 // One wave takes 64 samples per round (two 32-sample tiles, as the first

@@ -9,14 +9,22 @@
 //
 //   a = (2c y).x_i - c |x_i|^2 - c |y|^2,
 //
-// with FP32 accumulation. Both factors of the two products are split into a
-// high and a low half-precision part, and three of the four cross products
-// are kept (hi*hi + hi*lo + lo*hi), which leaves a relative error of about
-// 2^-22 (f16) or 2^-16 (bf16) per term. The feature order along K is
-//   [w_hi.x_hi (D) | w_hi.x_lo (D) | w_lo.x_hi (D) | nc_hi q_hi, nc_hi q_lo, nc_lo q_hi | S.1 | 0...]
+// with FP32 accumulation. The factors of the two products are split into
+// parts of the operand type (round to nearest even at every step):
+//  - half precision (11 significant bits): hi + lo, three of the four cross
+//    products kept (hi*hi + hi*lo + lo*hi), a relative error of about 2^-22
+//    per term; feature order along K
+//      [w_hi.x_hi (D) | w_hi.x_lo (D) | w_lo.x_hi (D) | nc_hi q_hi, nc_hi q_lo, nc_lo q_hi | S.1 | 0...]
+//  - bfloat16 (8 significant bits): hi + mid + lo, the six cross products of
+//    order up to two kept (hi*hi, hi*mid, hi*lo, mid*hi, mid*mid, lo*hi; the
+//    dropped ones are below 2^-26 of the term), feature order
+//      [w_hi.x_hi | w_hi.x_mid | w_hi.x_lo | w_mid.x_hi | w_mid.x_mid | w_lo.x_hi (D each) |
+//       nc_hi q_hi, nc_hi q_mid, nc_hi q_lo, nc_mid q_hi, nc_mid q_mid, nc_lo q_hi | S.1 | 0...]
 // with w = 2 c y, nc = -c, q = |x|^2; the point side of every K slot is a
 // precomputed record (16 bytes per lane-half per 16 K slots), the sample side
-// is formed in registers once per (sample, SNR). The per-sample constant
+// is formed in registers once per (sample, SNR). Either form is then limited
+// by the FP32 accumulation of the products, about 2^-24 of c (|y|^2 + |x|^2)
+// per addition. The per-sample constant
 // (K - c|y|^2 here, fed as the accumulator input; a rounded copy S in the
 // last slot in the first tier) carries no information: every output is a
 // difference of logarithms of the same sample's terms.
@@ -54,9 +62,11 @@ typedef float float16_t __attribute__((ext_vector_type(16)));
 
 constexpr int kTileLevels = kMaxBits - 5;   // label bits carried by the point-tile index
 
-// K slots used by a constellation of dimension D (3 D + 3 feature slots and
-// one slot for a per-sample shift), padded to whole products.
-__host__ __device__ constexpr int mfma_nk(int D) { return (3 * D + 4 + 15) / 16; }
+// K slots used by a constellation of dimension D (3 D + 3 feature slots in
+// half precision, 6 D + 6 in bfloat16, and one slot for a per-sample shift),
+// padded to whole products.
+__host__ __device__ constexpr int shift_slot(int D, bool bf) { return bf ? 6 * D + 6 : 3 * D + 3; }
+__host__ __device__ constexpr int mfma_nk(int D, bool bf = false) { return (shift_slot(D, bf) + 1 + 15) / 16; }
 
 template <bool BF> struct MfmaOp;
 template <> struct MfmaOp<false> {
@@ -74,13 +84,95 @@ template <> struct MfmaOp<true> {
   }
 };
 
-// hi + lo split of an FP32 value in the operand type (round to nearest even).
-template <bool BF>
-__device__ __forceinline__ void split2(float v, typename MfmaOp<BF>::elem& hi,
-                                       typename MfmaOp<BF>::elem& lo) {
-  typedef typename MfmaOp<BF>::elem E;
-  hi = (E)v;
-  lo = (E)(v - (float)hi);
+// hi + lo split of an FP32 value in half precision (round to nearest even).
+__device__ __forceinline__ void split2(float v, _Float16& hi, _Float16& lo) {
+  hi = (_Float16)v;
+  lo = (_Float16)(v - (float)hi);
+}
+
+// hi + mid + lo split of two FP32 values in bfloat16 (round to nearest even,
+// two values per conversion). Each remainder v - hi, (v - hi) - mid is exact
+// in FP32: a value minus its rounding to fewer significant bits.
+__device__ __forceinline__ void split3_bf16(float v0, float v1, __bf16 (&hi)[2], __bf16 (&mid)[2],
+                                            __bf16 (&lo)[2]) {
+  typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  const f2 v = {v0, v1};
+  const b2 h = __builtin_convertvector(v, b2);
+  const f2 r1 = v - __builtin_convertvector(h, f2);
+  const b2 md = __builtin_convertvector(r1, b2);
+  const f2 r2 = r1 - __builtin_convertvector(md, f2);
+  const b2 l = __builtin_convertvector(r2, b2);
+  hi[0] = h.x;
+  hi[1] = h.y;
+  mid[0] = md.x;
+  mid[1] = md.y;
+  lo[0] = l.x;
+  lo[1] = l.y;
+}
+
+// Sample-side features of the K slots (all but the shift slot) from
+// w = 2 c y and nc = -c, in the order of the point records; F must be zeroed.
+// Returns false when a value leaves the half-precision range (bfloat16 has
+// the FP32 range).
+template <int D, bool BF>
+__device__ __forceinline__ bool sample_features(const float (&w)[D], float nc, typename MfmaOp<BF>::elem* F) {
+  if constexpr (BF) {
+#pragma unroll
+    for (int d = 0; d < D; d += 2) {
+      const int d1 = d + 1 < D ? d + 1 : d;
+      __bf16 hi[2], mid[2], lo[2];
+      split3_bf16(w[d], d + 1 < D ? w[d1] : 0.0f, hi, mid, lo);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        if (d + i < D) {
+          F[d + i] = hi[i];
+          F[D + d + i] = hi[i];
+          F[2 * D + d + i] = hi[i];
+          F[3 * D + d + i] = mid[i];
+          F[4 * D + d + i] = mid[i];
+          F[5 * D + d + i] = lo[i];
+        }
+    }
+    __bf16 hi[2], mid[2], lo[2];
+    split3_bf16(nc, 0.0f, hi, mid, lo);
+    F[6 * D] = hi[0];
+    F[6 * D + 1] = hi[0];
+    F[6 * D + 2] = hi[0];
+    F[6 * D + 3] = mid[0];
+    F[6 * D + 4] = mid[0];
+    F[6 * D + 5] = lo[0];
+    return true;
+  } else {
+    // half precision: two dimensions at a time with the packed conversion
+    // (round to nearest even), which writes whole registers
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    bool ok = __builtin_fabsf(nc) < 60000.0f;
+#pragma unroll
+    for (int d = 0; d < D; d += 2) {
+      const float w0 = w[d];
+      const float w1 = d + 1 < D ? w[d + 1 < D ? d + 1 : d] : 0.0f;
+      ok &= __builtin_fmaxf(__builtin_fabsf(w0), __builtin_fabsf(w1)) < 60000.0f;
+      const f2 wv = {w0, w1};
+      const h2 hi = __builtin_convertvector(wv, h2);
+      const h2 lo = __builtin_convertvector(wv - __builtin_convertvector(hi, f2), h2);
+      F[d] = hi.x;
+      F[D + d] = hi.x;
+      F[2 * D + d] = lo.x;
+      if (d + 1 < D) {
+        F[d + 1] = hi.y;
+        F[D + d + 1] = hi.y;
+        F[2 * D + d + 1] = lo.y;
+      }
+    }
+    _Float16 hi, lo;
+    split2(nc, hi, lo);
+    F[3 * D] = hi;
+    F[3 * D + 1] = hi;
+    F[3 * D + 2] = lo;
+    return ok;
+  }
 }
 
 // The two values a lane pair (l, l + 32) holds: lo from lane l, hi from lane
@@ -178,7 +270,7 @@ template <int D, bool BF>
 struct SampleTile {
   typedef typename MfmaOp<BF>::vec V;
   typedef typename MfmaOp<BF>::elem E;
-  static constexpr int NK = mfma_nk(D);
+  static constexpr int NK = mfma_nk(D, BF);
   static constexpr int KP = 16 * NK;
   int64_t n;
   bool valid, live;
@@ -224,25 +316,10 @@ struct SampleTile {
     E F[KP];
 #pragma unroll
     for (int k = 0; k < KP; ++k) F[k] = (E)0.0f;
-    ovf = !(c < 60000.0f);
+    float w[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const float w = 2.0f * c * y[d];
-      ovf |= !(__builtin_fabsf(w) < 60000.0f);
-      E hi, lo;
-      split2<BF>(w, hi, lo);
-      F[d] = hi;
-      F[D + d] = hi;
-      F[2 * D + d] = lo;
-    }
-    if (BF) ovf = false;  // bfloat16 has the FP32 range
-    {
-      E hi, lo;
-      split2<BF>(-c, hi, lo);
-      F[3 * D] = hi;
-      F[3 * D + 1] = hi;
-      F[3 * D + 2] = lo;
-    }
+    for (int d = 0; d < D; ++d) w[d] = 2.0f * c * y[d];
+    ovf = !sample_features<D, BF>(w, -c, F);
     const uint32_t hmask = 0u - (uint32_t)h;
 #pragma unroll
     for (int kk = 0; kk < NK; ++kk) {
@@ -392,8 +469,8 @@ __device__ __forceinline__ const typename MfmaOp<BF>::vec* rec_row(const typenam
 }
 
 // Bytes of the block-local copies of the constellation tables.
-__host__ __device__ constexpr int64_t table_bytes(int M, int D) {
-  return (int64_t)M * 4 + (int64_t)M * D * 4 + 16 + (int64_t)M * mfma_nk(D) * 32;
+__host__ __device__ constexpr int64_t table_bytes(int M, int D, bool bf) {
+  return (int64_t)M * 4 + (int64_t)M * D * 4 + 16 + (int64_t)M * mfma_nk(D, bf) * 32;
 }
 
 // First tier of one sample tile: all point tiles through the matrix cores,

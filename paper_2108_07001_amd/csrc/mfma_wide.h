@@ -123,7 +123,7 @@ template <int D, bool BF>
 struct WideOperand {
   typedef typename MfmaOp<BF>::vec V;
   typedef typename MfmaOp<BF>::elem E;
-  static constexpr int NK = mfma_nk(D);
+  static constexpr int NK = mfma_nk(D, BF);
   static constexpr int KP = 16 * NK;
   V B[NK];
   bool ovf;      // a sample-side value outside the operand range: exact path
@@ -136,54 +136,17 @@ struct WideOperand {
     E F[KP];
 #pragma unroll
     for (int k = 0; k < KP; ++k) F[k] = (E)0.0f;
-    ovf = !(c < 60000.0f);
-    if constexpr (!BF) {
-      // half precision: split two dimensions at a time with the packed
-      // conversion (round to nearest even), which writes whole registers
-      typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-      typedef float f2 __attribute__((ext_vector_type(2)));
+    float w[D];
 #pragma unroll
-      for (int d = 0; d < D; d += 2) {
-        const float w0 = 2.0f * c * y[d];
-        const float w1 = d + 1 < D ? 2.0f * c * y[d + 1 < D ? d + 1 : d] : 0.0f;
-        ovf |= !(__builtin_fmaxf(__builtin_fabsf(w0), __builtin_fabsf(w1)) < 60000.0f);
-        const f2 w = {w0, w1};
-        const h2 hi = __builtin_convertvector(w, h2);
-        const h2 lo = __builtin_convertvector(w - __builtin_convertvector(hi, f2), h2);
-        F[d] = hi.x;
-        F[D + d] = hi.x;
-        F[2 * D + d] = lo.x;
-        if (d + 1 < D) {
-          F[d + 1] = hi.y;
-          F[D + d + 1] = hi.y;
-          F[2 * D + d + 1] = lo.y;
-        }
-      }
-    } else {
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        E hi, lo;
-        split2<BF>(2.0f * c * y[d], hi, lo);
-        F[d] = hi;
-        F[D + d] = hi;
-        F[2 * D + d] = lo;
-      }
-    }
-    {
-      E hi, lo;
-      split2<BF>(-c, hi, lo);
-      F[3 * D] = hi;
-      F[3 * D + 1] = hi;
-      F[3 * D + 2] = lo;
-    }
+    for (int d = 0; d < D; ++d) w[d] = 2.0f * c * y[d];
+    ovf = !sample_features<D, BF>(w, -c, F);
     // S = K - c|y|^2, rounded to the operand type from below: lowering the
     // argument by more than one unit in the last place before rounding to
     // nearest keeps the rounded value <= S
     const float s0 = __builtin_fmaf(-c, yy, K);
     const float ulp = BF ? 0x1p-7f : 0x1p-10f;
-    F[3 * D + 3] = (E)(s0 - __builtin_fabsf(s0) * ulp);
-    ovf |= !(__builtin_fabsf(s0) < 60000.0f);
-    if (BF) ovf = false;  // bfloat16 has the FP32 range
+    F[shift_slot(D, BF)] = (E)(s0 - __builtin_fabsf(s0) * ulp);
+    if (!BF) ovf |= !(__builtin_fabsf(s0) < 60000.0f);  // bfloat16 has the FP32 range
     const uint32_t hmask = 0u - (uint32_t)h;
 #pragma unroll
     for (int kk = 0; kk < NK; ++kk) {
@@ -658,7 +621,7 @@ template <int D, bool BF, bool ML>
 void launch_first_tier(const DemapArgs& a, const typename MfmaOp<BF>::vec* r, const float* x, int grid,
                        const Launch& l) {
   const uint32_t acc = (uint32_t)(sizeof(double) * 4 * a.S * 4);
-  const int64_t tbytes = table_bytes(a.M, D);
+  const int64_t tbytes = table_bytes(a.M, D, BF);
   const bool tbl = tbytes <= 40 * 1024;
   const uint32_t lds = acc + (uint32_t)tbytes;
   // the exact-size forms hold their tables in LDS (at most 12.5 KB for M = 64)
@@ -681,7 +644,7 @@ void launch_first_tier(const DemapArgs& a, const typename MfmaOp<BF>::vec* r, co
 template <int D, bool BF>
 hipError_t launch_mfma_wide_td(const DemapArgs& a, const void* rec, int grid, const Launch& l, int part) {
   const size_t acc = sizeof(double) * 4 * a.S * 4;
-  const int64_t tbytes = table_bytes(a.M, D);
+  const int64_t tbytes = table_bytes(a.M, D, BF);
   const bool tbl = tbytes <= 40 * 1024;
   typedef typename MfmaOp<BF>::vec V;
   const V* r = static_cast<const V*>(rec);

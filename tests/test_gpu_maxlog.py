@@ -12,7 +12,7 @@ from tests.helpers import MI_TOL, assert_llr, to_dev, tx_dev
 
 pytestmark = pytest.mark.gpu
 
-LLR_BAR = {"fp64": 1e-11, "fp32": 1e-3, "fp16x3": 1e-3, "bf16x3": 1e-2}
+LLR_BAR = {"fp64": 1e-11, "fp32": 1e-3, "fp16x3": 1e-3, "bf16x3": 1e-3}
 GMI_BAR = {"fp64": 1e-11, "fp32": MI_TOL, "fp16x3": MI_TOL, "bf16x3": MI_TOL}
 
 

@@ -12,10 +12,8 @@ from tests.helpers import assert_llr, assert_stats, llr_err, to_dev, tx_dev
 pytestmark = pytest.mark.gpu
 
 PRECS = ["fp16x3", "bf16x3"]
-# The 3-product bfloat16 split keeps ~2^-16 relative error per term: MI/GMI stay
-# inside 1e-4 bit, LLRs do not reach 1e-3 near L = 0 at high SNR. Its LLR bound
-# here is the measured characterisation; AIR_FP16X3 is held to the contract.
-LLR_BAR = {"fp16x3": 1e-3, "bf16x3": 1e-2}
+# Both split forms are held to the contract: |dL| <= 1e-3 max(|L|, 1 nat).
+LLR_BAR = {"fp16x3": 1e-3, "bf16x3": 1e-3}
 
 
 @pytest.fixture(scope="module")

@@ -14,8 +14,7 @@ from tests.helpers import assert_llr, to_dev
 
 pytestmark = pytest.mark.gpu
 
-# bfloat16 splits are a characterised variant (about 2^-16 per term), held to 1e-2
-LLR_BAR = {"fp64": 1e-11, "fp32": 1e-3, "fp16x3": 1e-3, "bf16x3": 1e-2}
+LLR_BAR = {"fp64": 1e-11, "fp32": 1e-3, "fp16x3": 1e-3, "bf16x3": 1e-3}
 
 
 @pytest.fixture(scope="module")

@@ -13,7 +13,7 @@ from tests.helpers import assert_llr, assert_stats, to_dev, tx_dev
 
 pytestmark = pytest.mark.gpu
 
-LLR_BAR = {"fp16x3": 1e-3, "bf16x3": 1e-2}
+LLR_BAR = {"fp16x3": 1e-3, "bf16x3": 1e-3}
 MIX = [(16, 2), (64, 4), (256, 4), (2048, 8)]     # (M, D) of the serving mix
 
 
