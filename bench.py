@@ -308,7 +308,7 @@ def serving(ctx, n_jobs: int) -> dict:
             txsrc = tx_dev if on_device else tx_host
             L = llr_pool[k, :jb.N * c.m].view(jb.N, c.m)
             jid = sv.submit(c=c, inp=zsrc[jb.D][:jb.N], tx=txsrc[jb.M][:jb.N], snr_db=jb.snr_db,
-                            noise=True, prec="fp16x3", llr=L, t_arrival_ns=t_arr)
+                            noise=True, prec="bf16x3", llr=L, t_arrival_ns=t_arr)
             slot_of[jid] = k
         sv.drain()
         reap()
@@ -337,9 +337,73 @@ def serving(ctx, n_jobs: int) -> dict:
             c.close()
     return {"workload": f"Poisson {spec['rate_hz']:g} jobs/s, M in {list(Ms)} (D {spec['D_for_M']}), "
                         f"N = 10^U({spec['N_log10'][0]},{spec['N_log10'][1]}), SNR U{tuple(spec['snr_db'])} dB, "
-                        f"fp16x3, LLRs to device memory",
+                        f"bf16x3, LLRs to device memory",
             "latency_from": "arrival time -> MI/GMI on the host",
             "host_inputs": host, "device_inputs": devr}
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def large_sets(ctx, names, steps: int) -> dict:
+    """Full-size step times of the large Gaussian sweeps: one air_sweep over
+    every sample and SNR point with LLRs written, per form (the matrix-core
+    forms `steps` timed steps after one warm-up, the plain FP32 kernel one),
+    with the first tier's kernel time and its fraction of the transcendental
+    roof, and the items the second tier and the exact path took."""
+    import torch
+    from paper_2108_07001_amd import air, inputs
+    out = {}
+    dev = ctx.torch_device
+    for name in names:
+        w = inputs.make(name)
+        M, m, N, S = w.M, w.m, w.N, len(w.snr_db)
+        c = ctx.const(w.X, w.labels)
+        tx = torch.from_numpy(w.tx.astype(np.int32)).to(dev)
+        z = torch.from_numpy(w.z).to(dev)
+        stats = torch.empty((S, 4), dtype=torch.float64, device=dev)
+        L = torch.empty((S, N, m), dtype=torch.float32, device=dev)
+        res = {"workload": f"{name}: {inputs.CONFIGS[name]['desc']}, N={N}, SNR {w.snr_db[0]:g}.."
+                           f"{w.snr_db[-1]:g} dB ({S} points), LLRs written (fp32)", "M": M, "D": w.D,
+               "N": N, "S": S}
+        trans = float(N) * S * (M + 2 * m + 1)
+        for p in ("fp16x3", "bf16x3", "fp32"):
+            k = steps if p != "fp32" else 1
+            ctx.sweep(c, tx, z, w.snr_db, prec=p, stats_out=stats, llr_out=L)
+            ctx.sync()
+            ctx.set_timing(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(k):
+                ctx.sweep(c, tx, z, w.snr_db, prec=p, stats_out=stats, llr_out=L)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / k
+            kms, nl = ctx.kernel_time()
+            ctx.set_timing(False)
+            kstep = kms / k                       # first-tier time per step (all its launches)
+            res[p] = {"ms_per_step": ms, "first_tier_ms_per_step": kstep,
+                      "sample_points_per_s": float(N) * S * M / (ms * 1e-3),
+                      "first_tier_trans_frac": trans / (kstep * 1e-3) / TRANS_PEAK,
+                      "step_trans_frac": trans / (ms * 1e-3) / TRANS_PEAK,
+                      "second_tier_items": int(ctx.last_recomputed()), "exact_path_items": int(ctx.last_exact()),
+                      "mi_gmi_first_last": [float(x) for x in stats.cpu().numpy()[[0, -1], :2].ravel()]}
+            log(f"{name} {p}: {ms:.2f} ms/step (first tier {kstep:.2f} ms), second tier "
+                f"{res[p]['second_tier_items']} items, exact {res[p]['exact_path_items']}")
+        for p in ("fp16x3", "bf16x3"):
+            res[p]["speedup_vs_fp32"] = res["fp32"]["ms_per_step"] / res[p]["ms_per_step"]
+        out[name] = res
+        del L, z, tx
+        c.close()
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -365,6 +429,13 @@ def main():
     ap.add_argument("--sq-from", default=None,
                     help="write profiles/sq_<config>_<prec>.json from a rocprofv3 --pmc run of "
                          "SQ counters of the benchmark under this directory, then exit")
+    ap.add_argument("--large-sets", default="gauss8d2048,gauss12d4096",
+                    help="large Gaussian sweeps whose full-size step times are reported beside the "
+                         "headline (comma-separated workload names; empty: skip)")
+    ap.add_argument("--large-steps", type=int, default=3,
+                    help="timed steps per matrix-core form of each large sweep (the plain FP32 kernel: 1)")
+    ap.add_argument("--roofs", action="store_true",
+                    help="only measure the unit rates (air_measure_roofs) and print them as JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device-to-device copy of 1 GiB (3 times), the "
                          "reference for scaling hardware byte counters")
@@ -410,6 +481,17 @@ def main():
         print(json.dumps({"copy_probe_bytes_read_per_launch": a.numel() * 4,
                           "copy_probe_bytes_written_per_launch": b.numel() * 4, "launches": 3}))
         return
+    if args.roofs:
+        from paper_2108_07001_amd import air
+        ctx = air.Context(0)
+        r = ctx.measure_roofs()
+        clk_cu = CLOCK_HZ * 256
+        r["per_cu_per_clock_at_2.4GHz"] = {"exp": r["exp_per_s"] / clk_cu, "explog": r["explog_per_s"] / clk_cu,
+                                           "fma": r["fma_per_s"] / clk_cu,
+                                           "mfma_f16_flop": r["mfma_f16_flops"] / clk_cu}
+        print(json.dumps(r), flush=True)
+        ctx.close()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
@@ -422,61 +504,75 @@ def main():
     w = inputs.make(args.config)
     M, D, m, N, S = w.M, w.D, w.m, w.N, len(w.snr_db)
     ctx = air.Context(0)
+    roofs = ctx.measure_roofs()
+    log(f"roofs: exp {roofs['exp_per_s']:.3e}/s, fma {roofs['fma_per_s']:.3e}/s, "
+        f"mfma f16 {roofs['mfma_f16_flops']:.3e} flop/s, copy {roofs['copy_bytes_per_s']:.3e} B/s")
     c = ctx.const(w.X, w.labels)
+    # the matrix-core forms first (the faster one that serves this
+    # constellation is the headline), the plain FP32 kernel as the baseline
     precs = ["fp16x3", "bf16x3", "fp32"] if args.prec is None else [args.prec]
+    if args.prec is None and args.no_fp32:
+        precs.remove("fp32")
     tx = torch.from_numpy(w.tx.astype(np.int32)).to(dev)
+    zt32 = torch.from_numpy(w.z).to(dev)
+    L = torch.empty((S, N, m), dtype=torch.float64 if "fp64" in precs else torch.float32, device=dev)
+    stats = torch.empty((S, 4), dtype=torch.float64, device=dev)
 
-    def run_prec(prec, steps, warmup):
-        zt = torch.from_numpy(w.z).to(dev)
-        if prec == "fp64":
-            zt = zt.double()
-        stats = torch.empty((S, 4), dtype=torch.float64, device=dev)
-        L = torch.empty((S, N, m), dtype=torch.float64 if prec == "fp64" else torch.float32,
-                        device=dev)
-        for _ in range(warmup):
-            ctx.sweep(c, tx, zt, w.snr_db, prec=prec, stats_out=stats, llr_out=L)
-        ctx.sync()
-        log(f"{prec}: warmup done")
-        recomputed = ctx.last_recomputed()
-        exact = ctx.last_exact()
-        ctx.set_timing(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            ctx.sweep(c, tx, zt, w.snr_db, prec=prec, stats_out=stats, llr_out=L)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        kms, launches = ctx.kernel_time()
-        ctx.set_timing(False)
-        ctx.sync()
-        ms = (t1 - t0) * 1e3 / steps
-        return dict(ms=ms, kernel_ms=kms / max(launches, 1), launches=launches / steps,
-                    stats=stats.cpu().numpy(), recomputed=recomputed, exact=exact)
+    def sweep(prec):
+        ctx.sweep(c, tx, zt32.double() if prec == "fp64" else zt32, w.snr_db, prec=prec,
+                  stats_out=stats, llr_out=L)
 
-    results = {}
-
-    def attempt(p, steps, warmup):
+    forms = []
+    for p in precs:
         try:
-            results[p] = run_prec(p, steps, warmup)
-            log(f"{p}: {results[p]['ms']:.3f} ms/step, kernel {results[p]['kernel_ms']:.3f} ms")
-            return True
+            sweep(p)
+            ctx.sync()
+            forms.append(p)
         except air.AirError as e:
             if e.status != air.AIR_E_UNSUPPORTED:
                 raise
             log(f"{p}: not available ({e})")
-            return False
-
-    # The comparison forms run first and the preferred form last: the GPU's
-    # clocks need some tens of milliseconds of load to settle, and the first
-    # timed kernels of a process run measurably slower.
-    if not args.no_fp32 and "fp32" not in precs:
-        attempt("fp32", max(3, args.steps // 4), 1)
-    for p in reversed(precs[1:]):
-        attempt(p, args.steps, args.warmup)
-    chosen = precs[0] if attempt(precs[0], args.steps, args.warmup) else \
-        next((p for p in precs[1:] if p in results), None)
-    if chosen is None:
+    if not forms:
         raise SystemExit("no precision form is available for this constellation")
+    # Untimed load first: the GPU's clocks need some hundreds of milliseconds
+    # of work to settle, and no form should absorb that. Then every form's
+    # warm-up, and the timed steps of the forms interleaved in rounds, so
+    # that slow drifts of the clock fall on all forms alike.
+    t_end = time.perf_counter() + 0.5
+    while time.perf_counter() < t_end:
+        for p in forms:
+            sweep(p)
+        torch.cuda.synchronize()
+    for p in forms:
+        for _ in range(args.warmup):
+            sweep(p)
+    ctx.sync()
+    results = {p: dict(ms=0.0, kms=0.0, launches=0) for p in forms}
+    rounds = min(4, args.steps)
+    ctx.set_timing(True)
+    for i in range(rounds):
+        k = args.steps // rounds + (1 if i < args.steps % rounds else 0)
+        for p in forms:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(k):
+                sweep(p)
+            torch.cuda.synchronize()
+            results[p]["ms"] += (time.perf_counter() - t0) * 1e3
+            kms, nl = ctx.kernel_time()
+            results[p]["kms"] += kms
+            results[p]["launches"] += nl
+    ctx.set_timing(False)
+    for p in forms:
+        r = results[p]
+        sweep(p)
+        r.update(recomputed=ctx.last_recomputed(), exact=ctx.last_exact(),
+                 ms=r["ms"] / args.steps, kernel_ms=r["kms"] / max(r["launches"], 1),
+                 launches=r["launches"] / args.steps, stats=stats.cpu().numpy())
+        log(f"{p}: {r['ms']:.3f} ms/step, kernel {r['kernel_ms']:.3f} ms")
+    chosen = min((p for p in forms if p != "fp32"), key=lambda p: results[p]["ms"], default=forms[0])
+    del L
+    torch.cuda.empty_cache()
 
     r = results[chosen]
     pts = float(N) * S * M
@@ -512,17 +608,29 @@ def main():
                      "algorithmic_per_launch": trans / max(r["launches"], 1)},
         "second_tier_items": int(r["recomputed"]),
         "exact_path_items": int(r["exact"]),
+        "roofs_measured": roofs,
     }
+    line["forms"] = {p: {"value": pts / (results[p]["ms"] * 1e-3), "ms_per_step": results[p]["ms"],
+                         "kernel_ms": results[p]["kernel_ms"], "second_tier_items": int(results[p]["recomputed"]),
+                         "exact_path_items": int(results[p]["exact"])} for p in forms}
     if chosen != "fp32" and "fp32" in results:
         f = results["fp32"]
         line["fp32_plain"] = {"value": pts / (f["ms"] * 1e-3), "ms_per_step": f["ms"],
                               "kernel_ms": f["kernel_ms"]}
         line["speedup_vs_fp32"] = f["ms"] / r["ms"]
+        for p in forms:
+            if p != "fp32":
+                line["forms"][p]["speedup_vs_fp32"] = f["ms"] / results[p]["ms"]
+    line["timing"] = (f"forms timed interleaved in {rounds} rounds after 0.5 s of untimed load and "
+                      f"{args.warmup} warm-up steps each; {args.steps} timed steps per form")
 
     if chosen in ("fp16x3", "bf16x3", "fp32"):
         line["maxlog"] = maxlog(ctx, c, w, tx, chosen, args.steps)
         line["maxlog"]["speedup_vs_exact"] = r["ms"] / line["maxlog"]["ms_per_step"]
     line["hard_decisions"] = hard_decisions(ctx, c, w, tx, max(3, args.steps // 4))
+
+    if args.large_sets:
+        line["large_sets"] = large_sets(ctx, [s for s in args.large_sets.split(",") if s], args.large_steps)
 
     if args.stream_buffers > 0:
         line["streaming"] = streaming(ctx, args.stream_buffers)
@@ -545,16 +653,23 @@ def main():
                                 "cores": oracle.threads(), "kind": "oracle",
                                 "sample": f"first {n} of {N} samples x {S} SNR points, LLRs on",
                                 "seconds": t_cpu}
-        # parity of the timed precision on the same prefix
+        line["cpu_baseline"]["cpu_model"] = cpu_model()
+        # parity of every timed form on the same prefix
         zt = torch.from_numpy(np.ascontiguousarray(w.z[:n])).to(dev)
-        st, Lg = ctx.sweep(c, tx[:n].contiguous(), zt, w.snr_db, prec=chosen, llr=True)
-        ctx.sync()
-        st = st.cpu().numpy()
-        Lg = Lg.cpu().numpy().astype(np.float64)
-        rel = np.abs(Lg - ref["llr"]) / np.maximum(np.abs(ref["llr"]), 1.0)
-        line["parity_vs_oracle"] = {"samples": n, "max_dMI_bits": float(np.abs(st[:, 0] - ref["stats"][:, 0]).max()),
-                                    "max_dGMI_bits": float(np.abs(st[:, 1] - ref["stats"][:, 1]).max()),
-                                    "max_llr_rel": float(rel.max())}
+        par = {}
+        for p in forms:
+            zp = zt.double() if p == "fp64" else zt
+            st, Lg = ctx.sweep(c, tx[:n].contiguous(), zp, w.snr_db, prec=p, llr=True)
+            ctx.sync()
+            st = st.cpu().numpy()
+            Lg = Lg.cpu().numpy().astype(np.float64)
+            rel = np.abs(Lg - ref["llr"]) / np.maximum(np.abs(ref["llr"]), 1.0)
+            par[p] = {"samples": n, "max_dMI_bits": float(np.abs(st[:, 0] - ref["stats"][:, 0]).max()),
+                      "max_dGMI_bits": float(np.abs(st[:, 1] - ref["stats"][:, 1]).max()),
+                      "max_llr_rel": float(rel.max())}
+            del Lg
+        line["parity_vs_oracle"] = par[chosen]
+        line["parity_vs_oracle_by_form"] = par
     print(json.dumps(line), flush=True)
     c.close()
     ctx.close()

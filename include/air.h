@@ -63,14 +63,16 @@ typedef enum {
 /* Arithmetic of the demapping kernels.
  *  AIR_FP64    FP64 throughout (distances, log-sum-exp, sums). Y / Z / LLR are double.
  *  AIR_FP32    FP32 vector ALU, squared distances by direct differences.
- *  AIR_BF16X3  exponent tile on the matrix cores from bfloat16 hi+lo splits
- *              (three products per term) with FP32 accumulation; FP32 log-sum-exp.
- *  AIR_FP16X3  as AIR_BF16X3 with half-precision hi+lo splits.
+ *  AIR_BF16X3  exponent tile on the matrix cores from bfloat16 splits of both
+ *              factors into hi + mid + lo parts (six cross products per term,
+ *              ~2^-24 relative) with FP32 accumulation; FP32 log-sum-exp.
+ *  AIR_FP16X3  the exponent tile from half-precision hi + lo splits (three
+ *              cross products per term, ~2^-22 relative); as AIR_BF16X3 otherwise.
  * Except AIR_FP64, Y / Z are float and LLRs float. Sums over samples are
  * always FP64. A result the fast FP32 frame cannot hold to the stated
  * accuracy (very large |LLR|, a received point far from every constellation
- * point) is recomputed: by the matrix-core forms' second tier with every
- * term in an FP64 frame, and beyond that (or in the vector forms) by an
+ * point) is recomputed: by a second tier with every term in an FP64 frame
+ * (AIR_FP32, AIR_BF16X3, AIR_FP16X3), and beyond that (or in AIR_FP64) by an
  * exact per-sample path relative to the nearest point. */
 typedef enum {
   AIR_FP64 = 0,
@@ -144,15 +146,15 @@ air_status air_sweep(air_ctx *ctx, const air_const *c, const uint32_t *tx_dev,
                      const void *Z_dev, int64_t N, const double *snr_db_host, int S,
                      air_prec prec, double *stats_dev, void *llr_dev);
 
-/* Number of (sample, SNR) items the last call on this context sent through
- * the exact recomputation (starved bit sides: |LLR| beyond the working type's
- * shifted range, or a received point far from every constellation point).
- * Synchronises. Returns -1 on error. */
+/* Number of (sample, SNR) items the last call on this context did not finish
+ * in its first tier's sums (starved bit sides: |LLR| beyond the FP32 frame's
+ * range, or a received point far from every constellation point): finished by
+ * the second tier or the exact path. Synchronises. Returns -1 on error. */
 int64_t air_last_recomputed(air_ctx *ctx);
 
-/* Of those items, the number that needed the exact path (beyond the
- * matrix-core forms' FP64 second-tier window, |LLR| of roughly 1300 nats; for
- * the vector kernels every recomputed item). Synchronises. -1 on error. */
+/* Of those items, the number that needed the exact path (beyond the FP64
+ * second-tier window, |LLR| of roughly 1300 nats; for AIR_FP64 every
+ * recomputed item). Synchronises. -1 on error. */
 int64_t air_last_exact(air_ctx *ctx);
 
 /* Kernel timing for measurement tools. While enabled, each launch of a call's
@@ -167,6 +169,27 @@ air_status air_set_timing(air_ctx *ctx, int enable);
  * last read (ms), and the number of launches; synchronises, then discards the
  * recorded pairs. */
 air_status air_kernel_time(air_ctx *ctx, double *total_ms, int64_t *launches);
+
+/* Rates of the units that bound the demapping path on the context's device,
+ * measured by microbenchmark kernels (each timed with HIP events after one
+ * untimed launch; all CUs busy, independent chains per lane). For measurement
+ * tools: the roof fractions reported for the demapping kernels are taken
+ * against these units. */
+typedef struct {
+  double exp_per_s;          /* v_exp_f32 results per second                               */
+  double explog_per_s;       /* exp2 and log2 in turn: transcendental results per second  */
+  double fma_per_s;          /* FP32 FMA results per second (non-packed)                  */
+  double exp_fma_ratio[3];   /* time of (1 exp2 + K FMAs), K = 1, 2, 4, over the sum of the
+                                two kinds' separate times: 1 = they share one issue budget,
+                                ~0.5 = they overlap fully                                   */
+  double mfma_f16_flops;     /* v_mfma_f32_32x32x16_f16, flop/s                            */
+  double mfma_bf16_flops;    /* v_mfma_f32_32x32x16_bf16, flop/s                           */
+  double copy_bytes_per_s;   /* bytes read + written per second by a 1 GiB device copy     */
+} air_roofs;
+
+/* Run the microbenchmarks on the context's stream (about 0.1 s; allocates and
+ * frees 2 GiB of device memory and synchronises). */
+air_status air_measure_roofs(air_ctx *ctx, air_roofs *out);
 
 /* ---------------------------------------------------------------------------
  * Auxiliary-channel (mismatched) rates. The paper measures a real link and

@@ -55,6 +55,14 @@ class AirServerInfo(ctypes.Structure):
                 ("max_batch", ctypes.c_int32), ("queued", ctypes.c_int32)]
 
 
+class AirRoofs(ctypes.Structure):
+    """air_roofs of include/air.h."""
+    _fields_ = [("exp_per_s", ctypes.c_double), ("explog_per_s", ctypes.c_double),
+                ("fma_per_s", ctypes.c_double), ("exp_fma_ratio", ctypes.c_double * 3),
+                ("mfma_f16_flops", ctypes.c_double), ("mfma_bf16_flops", ctypes.c_double),
+                ("copy_bytes_per_s", ctypes.c_double)]
+
+
 class AirError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -102,6 +110,8 @@ def load() -> ctypes.CDLL:
     lib.air_set_timing.restype = ci
     lib.air_kernel_time.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     lib.air_kernel_time.restype = ci
+    lib.air_measure_roofs.argtypes = [vp, ctypes.POINTER(AirRoofs)]
+    lib.air_measure_roofs.restype = ci
     lib.air_llr_maxlog.argtypes = [vp, vp, vp, i64, dbl, ci, vp]
     lib.air_llr_maxlog.restype = ci
     lib.air_gmi_maxlog.argtypes = [vp, vp, vp, vp, i64, dbl, ci, vp, vp]
@@ -243,6 +253,16 @@ class Context:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         self.check(self.lib.air_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def measure_roofs(self) -> dict:
+        """air_measure_roofs: measured rates of the units bounding the path."""
+        r = AirRoofs()
+        self.check(self.lib.air_measure_roofs(self.h, ctypes.byref(r)))
+        return {"exp_per_s": r.exp_per_s, "explog_per_s": r.explog_per_s, "fma_per_s": r.fma_per_s,
+                "exp_fma_ratio": {"K1": r.exp_fma_ratio[0], "K2": r.exp_fma_ratio[1],
+                                  "K4": r.exp_fma_ratio[2]},
+                "mfma_f16_flops": r.mfma_f16_flops, "mfma_bf16_flops": r.mfma_bf16_flops,
+                "copy_bytes_per_s": r.copy_bytes_per_s}
 
     def close(self):
         if getattr(self, "h", None):

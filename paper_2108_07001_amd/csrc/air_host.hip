@@ -16,9 +16,11 @@
 
 namespace air {
 
-// Vector-kernel launchers, one per (type, D), defined in vec_inst_*.hip.
-using VecFn = hipError_t (*)(const DemapArgs&, int, const Launch&, bool);
-#define AIR_DECL(tag, D) hipError_t launch_vec_##tag##_d##D(const DemapArgs&, int, const Launch&, bool);
+// Vector-kernel launchers, one per (type, D), defined in vec_inst_*.hip
+// (arguments: launch, grid, where, max-log form, part: 0 the first tier, 1
+// the FP32 second tier).
+using VecFn = hipError_t (*)(const DemapArgs&, int, const Launch&, bool, int);
+#define AIR_DECL(tag, D) hipError_t launch_vec_##tag##_d##D(const DemapArgs&, int, const Launch&, bool, int);
 #define AIR_DECL_ALL(tag)                                                                        \
   AIR_DECL(tag, 1) AIR_DECL(tag, 2) AIR_DECL(tag, 3) AIR_DECL(tag, 4) AIR_DECL(tag, 5)          \
   AIR_DECL(tag, 6) AIR_DECL(tag, 7) AIR_DECL(tag, 8) AIR_DECL(tag, 9) AIR_DECL(tag, 10)         \
@@ -374,12 +376,18 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
   a.m = c->m;
   a.D = c->D;
   a.sweep = sweep;
-  if (mfma) {
-    // per (SNR point, wave) a run of list slots, one per sample tile the wave owns
+  // the FP32 vector kernel's exact form (AIR_FP32, and the matrix-core
+  // precisions on sets of fewer than 16 points) also has a second tier
+  const bool vec_t2 = !mfma && !fp64 && !maxlog;
+  if (mfma || vec_t2) {
+    // per (SNR point, wave) a run of list slots, one per sample tile the wave
+    // owns (matrix cores: pairs of tiles dealt out to the waves; vector
+    // kernel: two tiles per wave and round, every slot written)
     const int64_t ntiles = (N + 31) / 32;
     const int64_t waves = (int64_t)grid * 4;
     const int64_t npairs = (ntiles + 1) / 2;
-    const int64_t tpw = 2 * ((npairs + waves - 1) / waves);
+    const int64_t stride = (int64_t)grid * kBlock;
+    const int64_t tpw = mfma ? 2 * ((npairs + waves - 1) / waves) : 2 * ((N + stride - 1) / stride);
     // tile indices and per-SNR sample counts of the second tier are 32-bit
     if (N >= ((int64_t)1 << 32)) return fail(ctx, AIR_E_UNSUPPORTED, "N too large for one call");
     const int64_t sl = S < kMaxSnrPerLaunch ? S : kMaxSnrPerLaunch;
@@ -422,11 +430,12 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
       lt.stop = ctx->ev[ctx->ev_used + 1];
       ctx->ev_used += 2;
     }
-    e = mfma ? mfn(a, rec, grid, lt, maxlog ? 2 : 0) : vfn(a, grid, lt, maxlog);
+    e = mfma ? mfn(a, rec, grid, lt, maxlog ? 2 : 0) : vfn(a, grid, lt, maxlog, 0);
     if (e != hipSuccess) return hip_fail(ctx, e, "demapping kernel launch");
-    const bool tier2 = mfma && !maxlog;
+    const bool tier2 = (mfma && !maxlog) || vec_t2;
     if (tier2) {
-      e = mfn(a, rec, grid, Launch{ctx->stream, nullptr, nullptr}, 1);
+      const Launch l2{ctx->stream, nullptr, nullptr};
+      e = mfma ? mfn(a, rec, grid, l2, 1) : vfn(a, grid, l2, false, 1);
       if (e != hipSuccess) return hip_fail(ctx, e, "second-tier launch");
     }
     hipLaunchKernelGGL(finish_kernel, dim3(ns), dim3(256), 0, ctx->stream, ctx->partials,

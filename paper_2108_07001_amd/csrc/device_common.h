@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "exact_rule.h"
+
 namespace air {
 
 constexpr int kMaxSnrPerLaunch = 64;
@@ -84,7 +86,7 @@ struct DemapArgs {
   int64_t llr_stride_s;             // elements between consecutive SNR planes of llr
   int M, m, D, S;
   int sweep;                        // 1: y = x_t + sigma_s z from `in`
-  // second tier of the matrix-core path (unused by the vector kernels)
+  // second tier (matrix-core forms and the FP32 vector kernel)
   unsigned long long* t2_list;      // [S][waves][tpw]: sample tile (32 bits) | lane mask (32)
   double* t2_partials;              // [S][4][gridDim.x], as partials, from the second tier
   int t2_tpw;                       // list slots per (SNR point, wave)
@@ -243,12 +245,34 @@ __device__ __forceinline__ ExactArgs<T> exact_args(const DemapArgs& a, int s) {
                       Real<T>::sigma(a.snr, s), Real<T>::c(a.snr, s), a.recomputed};
 }
 
-// Outputs of one (sample, SNR) item from its fast-path sums.
+// Outputs of one (sample, SNR) item whose fast-path sums are all above the
+// starvation bound: the m LLRs (if llr_out) and u, v (when tl >= 0).
 //  total:   sum_j 2^arg_j;  side[2k+b]: the same over bit side (k, b).
-//  arg_t:   arg of the transmitted point (used when tl >= 0).
-// Writes the m LLRs (if llr_out) and returns u, v through the references.
-// Entries below the starvation bound are recomputed exactly; the return value
-// says whether that happened (the caller counts such items).
+//  arg_t:   arg of the transmitted point.
+template <typename T>
+__device__ __forceinline__ void finish_fast(int m, int tl, T total, const T (&side)[2 * kMaxBits], T arg_t,
+                                            T* llr_out, T& u, T& v) {
+  const T lam_tot = Real<T>::log2(total);
+  T acc = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxBits; ++k) {
+    if (k < m) {
+      const T l0 = Real<T>::log2(side[2 * k]), l1 = Real<T>::log2(side[2 * k + 1]);
+      if (llr_out) llr_out[k] = Real<T>::ln2() * (l0 - l1);
+      acc += lam_tot - (((tl >> k) & 1) ? l1 : l0);
+    }
+  }
+  if (tl >= 0) {
+    // log2 of the very term that entered the sum (not arg_t itself): u >= 0
+    // then holds exactly, whatever the rounding of exp2 and log2.
+    u = lam_tot - Real<T>::log2(Real<T>::exp2(arg_t));
+    v = acc;
+  }
+}
+
+// Outputs of one (sample, SNR) item from its fast-path sums, as finish_fast,
+// with the entries below the starvation bound recomputed exactly; the return
+// value says whether that happened (the caller counts such items).
 template <typename T, int D>
 __device__ __forceinline__ bool finish_item(const ExactArgs<T>& a, int64_t n, int tl,
                                             T total, const T (&side)[2 * kMaxBits], T arg_t,
@@ -270,8 +294,9 @@ __device__ __forceinline__ bool finish_item(const ExactArgs<T>& a, int64_t n, in
   T delta_t = 0;
   if (slow) {
     // Starved entries are recomputed relative to the nearest point r. If the
-    // total itself is starved every entry is (each side is below the total),
-    // and all of them stay relative to a_r; otherwise the recomputed sides are
+    // total itself is starved, every entry is recomputed and all stay
+    // relative to a_r (a side need not be below the total bit for bit: the
+    // two are summed in different orders); otherwise the recomputed sides are
     // put back in the fast path's units by adding K + a_r, which is then small.
     const T* in = a.in;
     const T* xl = a.xl;
@@ -287,9 +312,10 @@ __device__ __forceinline__ bool finish_item(const ExactArgs<T>& a, int64_t n, in
       reload_point<T, D>(in, a.sweep, xl, sigma, n, tl, y);
       base = Real<T>::shift(m) - c * sqdist<T, D>(y, xl + (int64_t)r * D);
     }
+    const uint32_t redo = exact_entries<T>(total, side, m, thr);
 #pragma unroll
     for (int i = 0; i < 2 * kMaxBits; ++i)
-      if (i < 2 * m && !(side[i] >= thr))
+      if (i < 2 * m && ((redo >> i) & 1u))
         lam[i] = base + slow_rel<T, D>(in, a.sweep, xl, a.M, sigma, c, n, tl, r, i >> 1, i & 1);
   }
   if (llr_out) {
@@ -350,10 +376,11 @@ __device__ __forceinline__ void finish_item_frame64(const ExactArgs<float>& a, i
     base = (double)K64 - (double)c * (double)sqdist<float, D>(y, xl + (int64_t)r * D);
     lam_tot = log2_wide(total);
   }
+  const uint32_t redo = exact_entries<double>(total, side, m, thr64);
 #pragma unroll
   for (int i = 0; i < 2 * kMaxBits; ++i) {
     if (i < 2 * m) {
-      if (total_slow || !(side[i] >= thr64))
+      if ((redo >> i) & 1u)
         lam[i] = base + (double)slow_rel<float, D>(in, a.sweep, xl, a.M, sigma, c, n, tl, r, i >> 1, i & 1);
       else
         lam[i] = log2_wide(side[i]);

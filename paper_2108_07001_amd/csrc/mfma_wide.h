@@ -604,17 +604,6 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
   }
 }
 
-// Blocks of a second-tier launch: at most 512 (2048 waves, one round of the
-// chip at two waves per SIMD); the gathered list is spread over them evenly.
-__host__ __device__ inline int t2_grid(int grid) { return grid < 512 ? grid : 512; }
-
-// The first tier's flagged samples gathered per SNR point, with their counts.
-inline void launch_t2_collect(const DemapArgs& a, int grid, hipStream_t st) {
-  const int W = grid * 4;
-  hipLaunchKernelGGL(t2_collect, dim3((unsigned)((W + 255) / 256), (unsigned)a.S), dim3(256), 0, st, a.t2_nitem,
-                     a.t2_list, W, a.t2_tpw, a.t2_cap, a.t2_tot, a.t2_items);
-}
-
 // The wide first tier (exact or max-log) in the variant the constellation
 // size calls for.
 template <int D, bool BF, bool ML>

@@ -4,8 +4,8 @@
 
 namespace air {
 #define AIR_VEC_INST(D) \
-  hipError_t launch_vec_f64_d##D(const DemapArgs& a, int g, const Launch& l, bool ml) { \
-    return launch_vec_td<double, D>(a, g, l, ml); \
+  hipError_t launch_vec_f64_d##D(const DemapArgs& a, int g, const Launch& l, bool ml, int part) { \
+    return launch_vec_td<double, D>(a, g, l, ml, part); \
   }
 AIR_VEC_INST(9)
 AIR_VEC_INST(10)

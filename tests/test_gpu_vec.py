@@ -176,3 +176,58 @@ def test_many_snr_points_span_launches(ctx):
     ref = oracle.sweep(w.X, w.labels, w.tx, w.z, w.snr_db)
     assert_stats(stats, ref["stats"], se_rel=2e-2)
     assert_llr(L, ref["llr"])
+
+
+def test_fp32_second_tier_frame64_window(ctx):
+    """8-D, M = 2048 at 16..24 dB: |LLR| of several hundred nats, beyond the
+    FP32 frame; those items are finished by the FP32 vector kernel's second
+    tier in the FP64 frame (few or none need the exact path)."""
+    w = inputs.make("gauss8d2048", N=3000 + 37, snr_db=[16.0, 20.0, 24.0])
+    stats, L, _ = _sweep(ctx, w, "fp32")
+    rec, exact = ctx.last_recomputed(), ctx.last_exact()
+    ref = oracle.sweep(w.X, w.labels, w.tx, w.z, w.snr_db)
+    print(f"second tier {rec} of {w.N * 3} items, exact path {exact}, max |L| {np.abs(ref['llr']).max():.0f}")
+    assert_stats(stats, ref["stats"])
+    assert_llr(L, ref["llr"])
+    assert rec > 0 and exact < rec
+
+
+@pytest.mark.parametrize("M,D,N", [(2, 1, 1), (8, 2, 65), (64, 4, 1000 + 37), (256, 3, 257)])
+def test_fp32_second_tier_shapes_and_launches(ctx, M, D, N):
+    """Second-tier items in ragged tails, at every group size (M < 16 too) and
+    over 70 SNR points up to 45 dB (two launches, each with its own lists)."""
+    X, lab = inputs.random_constellation(M + D, M, D)
+    tx, z = inputs.random_block(N + M, M, N, D)
+    w = inputs.Workload("t", X, lab, tx, z, np.linspace(-5.0, 45.0, 70))
+    stats, L, _ = _sweep(ctx, w, "fp32")
+    rec = ctx.last_recomputed()
+    ref = oracle.sweep(X, lab, tx, z, w.snr_db)
+    assert_stats(stats, ref["stats"], se_rel=2e-2)
+    assert_llr(L, ref["llr"])
+    assert rec > 0
+
+
+def test_fp32_second_tier_counts_and_results_repeat(ctx):
+    """The second tier's lists and counts start clean on every call: results
+    and counts repeat bit for bit across calls of different sizes and SNRs."""
+    hi = inputs.make("psk8x8", N=20_000, snr_db=[30.0, 40.0])
+    lo = inputs.make("psk8x8", N=5_000, snr_db=[-2.0])
+    c = ctx.const(hi.X, hi.labels)
+
+    def run(wl):
+        st, L = ctx.sweep(c, tx_dev(wl.tx), to_dev(wl.z), wl.snr_db, prec="fp32", llr=True)
+        ctx.sync()
+        return st.cpu().numpy(), L.cpu().numpy(), ctx.last_recomputed(), ctx.last_exact()
+
+    a = run(hi)
+    assert a[2] > 0
+    b = run(lo)
+    assert b[2] == 0 and b[3] == 0
+    for _ in range(2):
+        a2 = run(hi)
+        assert np.array_equal(a2[0], a[0]) and np.array_equal(a2[1], a[1]) and a2[2:] == a[2:]
+        b2 = run(lo)
+        assert np.array_equal(b2[0], b[0]) and b2[2:] == b[2:]
+    ref = oracle.sweep(hi.X, hi.labels, hi.tx, hi.z, hi.snr_db)
+    assert_stats(a[0], ref["stats"])
+    assert_llr(a[1], ref["llr"])
