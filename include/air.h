@@ -146,6 +146,26 @@ air_status air_sweep(air_ctx *ctx, const air_const *c, const uint32_t *tx_dev,
                      const void *Z_dev, int64_t N, const double *snr_db_host, int S,
                      air_prec prec, double *stats_dev, void *llr_dev);
 
+/* air_sweep for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc. The
+ * same computation, arguments, layouts and errors as air_sweep; it calls no
+ * hipMalloc / hipFree or other allocating routine, and launches untimed
+ * (air_set_timing does not apply). The second tier's per-launch workspace
+ * comes from one 48 MiB device array per GPU, allocated with the library's
+ * code on that GPU and kept until the process ends; a launch takes as many
+ * SNR points (at most 64) as fit in it: per point about 4.3 bytes per sample
+ * plus up to 1.7 MB for the launch's waves (5 MB at N = 1e6). N beyond what
+ * one SNR point fits (about 1.1e7 samples) returns AIR_E_INVAL before any
+ * launch. Every call on a GPU shares that GPU's array: calls that can overlap
+ * on one GPU (other contexts or streams) race and must be ordered by the
+ * caller. Each launch writes every
+ * part of the array it reads before reading it, so nothing carries over
+ * between calls. Requires that a context was created on the device
+ * (air_create looks the array up); AIR_E_DEVICE otherwise. */
+air_status air_sweep_noalloc(air_ctx *ctx, const air_const *c, const uint32_t *tx_dev,
+                             const void *Z_dev, int64_t N, const double *snr_db_host, int S,
+                             air_prec prec, double *stats_dev, void *llr_dev);
+
 /* Number of (sample, SNR) items the last call on this context did not finish
  * in its first tier's sums (starved bit sides: |LLR| beyond the FP32 frame's
  * range, or a received point far from every constellation point): finished by

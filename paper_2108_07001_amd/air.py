@@ -102,6 +102,8 @@ def load() -> ctypes.CDLL:
     lib.air_mi_gmi.restype = ci
     lib.air_sweep.argtypes = [vp, vp, vp, vp, i64, vp, ci, ci, vp, vp]
     lib.air_sweep.restype = ci
+    lib.air_sweep_noalloc.argtypes = [vp, vp, vp, vp, i64, vp, ci, ci, vp, vp]
+    lib.air_sweep_noalloc.restype = ci
     lib.air_last_recomputed.argtypes = [vp]
     lib.air_last_recomputed.restype = i64
     lib.air_last_exact.argtypes = [vp]
@@ -459,6 +461,15 @@ class Context:
         self.check(getattr(self.lib, _fn)(self.h, c.h, _ptr(tx), _ptr(Z), N, snr.ctypes.data, S,
                                           PREC[prec], _ptr(stats), _ptr(L)))
         return stats, L
+
+    def sweep_noalloc(self, c: Const, tx: torch.Tensor, Z: torch.Tensor, snr_db: Sequence[float],
+                      prec: str = "fp32", stats_out: torch.Tensor = None, llr_out: torch.Tensor = None):
+        """air_sweep_noalloc: as sweep, with caller-allocated outputs (the call
+        allocates no device memory)."""
+        if stats_out is None:
+            raise AirError(AIR_E_INVAL, "sweep_noalloc needs stats_out")
+        return self.sweep(c, tx, Z, snr_db, prec=prec, stats_out=stats_out, llr_out=llr_out,
+                          _fn="air_sweep_noalloc")
 
 
 def _buffer(x, dtype, shape, name: str, device: torch.device):

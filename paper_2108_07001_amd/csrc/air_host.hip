@@ -181,6 +181,9 @@ __global__ void fold_error_kernel(const CallWords* call, CallWords* next, int* s
   }
 }
 
+// noalloc.hip: looks up the no-allocation scratch array's address on a device.
+hipError_t noalloc_scratch_init(int device);
+
 }  // namespace air
 
 using namespace air;
@@ -333,9 +336,13 @@ hipError_t begin_call(air_ctx* ctx, CallWords** next) {
 bool prec_ok(air_prec p) { return p == AIR_FP64 || p == AIR_FP32 || p == AIR_BF16X3 || p == AIR_FP16X3; }
 
 // Common driver of air_llr / air_mi_gmi / air_sweep.
+// With `scratch` (scratch_bytes of device memory), the second tier's lists,
+// counts and gathered samples of each launch are carved from it instead of
+// the context's workspace, no timing events are created, and each launch
+// takes as many SNR points as fit (air_sweep_noalloc): nothing is allocated.
 air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t* tx, int64_t N,
                const double* snr_db, int S, int sweep, air_prec prec, double* stats, void* llr,
-               bool aux = false, bool maxlog = false) {
+               bool aux = false, bool maxlog = false, void* scratch = nullptr, size_t scratch_bytes = 0) {
   if (!ctx) return AIR_E_INVAL;
   if (!c || c->ctx != ctx) return fail(ctx, AIR_E_INVAL, "constellation is null or from another context");
   if (!in) return fail(ctx, AIR_E_INVAL, sweep ? "Z_dev is null" : "Y_dev is null");
@@ -379,6 +386,7 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
   // the FP32 vector kernel's exact form (AIR_FP32, and the matrix-core
   // precisions on sets of fewer than 16 points) also has a second tier
   const bool vec_t2 = !mfma && !fp64 && !maxlog;
+  int snr_per_launch = kMaxSnrPerLaunch;
   if (mfma || vec_t2) {
     // per (SNR point, wave) a run of list slots, one per sample tile the wave
     // owns (matrix cores: pairs of tiles dealt out to the waves; vector
@@ -390,14 +398,34 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
     const int64_t tpw = mfma ? 2 * ((npairs + waves - 1) / waves) : 2 * ((N + stride - 1) / stride);
     // tile indices and per-SNR sample counts of the second tier are 32-bit
     if (N >= ((int64_t)1 << 32)) return fail(ctx, AIR_E_UNSUPPORTED, "N too large for one call");
-    const int64_t sl = S < kMaxSnrPerLaunch ? S : kMaxSnrPerLaunch;
-    const air_status st = ensure_t2(ctx, sl * waves * tpw, sl * waves);
-    if (st != AIR_OK) return st;
-    a.t2_list = ctx->t2_list;
+    if (scratch) {
+      // per SNR point of a launch: list slots (8 bytes), flagged counts per
+      // wave (4) and 32 gathered sample indices per slot (4 each); three
+      // parts, each starting on a 256-byte boundary
+      const int64_t per_snr = waves * tpw * 8 + waves * 4 + waves * tpw * 32 * 4;
+      const int64_t avail = (int64_t)scratch_bytes - 3 * 256;
+      const int64_t fit = avail > 0 ? avail / per_snr : 0;
+      if (fit < 1)
+        return fail(ctx, AIR_E_INVAL, "N too large for air_sweep_noalloc: one SNR point needs " +
+                                          std::to_string(per_snr) + " bytes of its " +
+                                          std::to_string(scratch_bytes) + "-byte scratch");
+      snr_per_launch = (int)(fit < kMaxSnrPerLaunch ? fit : kMaxSnrPerLaunch);
+      const int64_t sl = snr_per_launch;
+      auto up = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+      char* base = static_cast<char*>(scratch);
+      a.t2_list = reinterpret_cast<unsigned long long*>(base);
+      a.t2_nitem = reinterpret_cast<unsigned int*>(base + up(sl * waves * tpw * 8));
+      a.t2_items = reinterpret_cast<uint32_t*>(base + up(sl * waves * tpw * 8) + up(sl * waves * 4));
+    } else {
+      const int64_t sl = S < kMaxSnrPerLaunch ? S : kMaxSnrPerLaunch;
+      const air_status st = ensure_t2(ctx, sl * waves * tpw, sl * waves);
+      if (st != AIR_OK) return st;
+      a.t2_list = ctx->t2_list;
+      a.t2_nitem = ctx->t2_nitem;
+      a.t2_items = ctx->t2_items;
+    }
     a.t2_partials = ctx->t2_partials;
     a.t2_tpw = (int)tpw;
-    a.t2_nitem = ctx->t2_nitem;
-    a.t2_items = ctx->t2_items;
     a.t2_cap = waves * tpw * 32;
     a.t2_tot = ctx->t2_tot;
   }
@@ -407,8 +435,8 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
   a.err = &ctx->call->err;
   a.recomputed = &ctx->call->recomputed;
   a.exact = &ctx->call->exact;
-  for (int s0 = 0; s0 < S; s0 += kMaxSnrPerLaunch) {
-    const int ns = (S - s0 < kMaxSnrPerLaunch) ? S - s0 : kMaxSnrPerLaunch;
+  for (int s0 = 0; s0 < S; s0 += snr_per_launch) {
+    const int ns = (S - s0 < snr_per_launch) ? S - s0 : snr_per_launch;
     a.S = ns;
     fill_snr(a.snr, c, snr_db + s0, ns, aux);
     a.llr = llr ? (void*)((char*)llr + (size_t)s0 * N * c->m * tsz) : nullptr;
@@ -417,7 +445,7 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
     // write-back that idles the stream around the kernel: 5.8 -> 2.3 us per
     // 8-PSK^2 step)
     Launch lt{ctx->stream, nullptr, nullptr};
-    if (ctx->timing) {
+    if (ctx->timing && !scratch) {
       if (ctx->ev_used + 2 > ctx->ev.size()) {
         for (int k = 0; k < 2; ++k) {
           hipEvent_t ev;
@@ -448,6 +476,21 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
   ctx->err.clear();
   return AIR_OK;
 }
+
+}  // namespace
+
+namespace air {
+
+// The sweep with a caller-supplied second-tier workspace (noalloc.hip).
+air_status run_sweep_scratch(air_ctx* ctx, const air_const* c, const void* Z, const uint32_t* tx, int64_t N,
+                             const double* snr_db, int S, air_prec prec, double* stats, void* llr,
+                             void* scratch, size_t scratch_bytes) {
+  return run(ctx, c, Z, tx, N, snr_db, S, 1, prec, stats, llr, false, false, scratch, scratch_bytes);
+}
+
+}  // namespace air
+
+namespace {
 
 // Driver of air_hard_decide / air_hard_sweep.
 air_status run_hd(air_ctx* ctx, const air_const* c, const float* in, const uint32_t* tx, int64_t N,
@@ -574,6 +617,9 @@ air_status air_create(air_ctx** out, int device, void* hip_stream) {
     ctx->call = ctx->calls;
     if (e == hipSuccess) e = hipMemset(ctx->sticky, 0, sizeof(int));
     if (e == hipSuccess) e = hipDeviceSynchronize();
+    // the no-allocation entry point's scratch on this device (looked up once
+    // per device; if that fails, air_sweep_noalloc reports it)
+    if (e == hipSuccess) (void)noalloc_scratch_init(device);
     if (e != hipSuccess) {
       air_destroy(ctx);
       return e == hipErrorOutOfMemory ? AIR_E_NOMEM : AIR_E_DEVICE;

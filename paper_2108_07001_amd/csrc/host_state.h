@@ -13,6 +13,11 @@
 
 constexpr int kSmallDoubles = 32;
 
+// air_sweep_noalloc: devices served and the size of its per-GPU scratch array
+// (the second tier's lists, counts and gathered samples of one launch).
+constexpr int kMaxDevices = 64;
+constexpr size_t kNoAllocScratchBytes = (size_t)48 << 20;
+
 struct air_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
