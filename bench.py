@@ -445,7 +445,8 @@ def main():
         w0 = inputs_config(args.config)
         kern = FIRST_TIER_KERNEL.format(D=w0["D"], BF="true" if prec == "bf16x3" else "false",
                                         MB={16: 4, 32: 5, 64: 6}.get(w0["M"], 0))
-        run = f"python3 bench.py --config {args.config} --no-cpu --serving-jobs 0 --stream-buffers 0"
+        run = (f"python3 bench.py --config {args.config} --no-cpu --serving-jobs 0 --stream-buffers 0 "
+               f"--large-sets ''")
         cmds = [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/f -o f -- {run}",
                 f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/w -o w -- {run}",
                 "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/cf -o cf -- python3 bench.py --copy-probe",
@@ -465,7 +466,7 @@ def main():
         d.update(kernel=kern, workload=args.config, prec=prec, source_hash=source_hash(),
                  commands=[f"rocprofv3 --pmc {' '.join(sorted(k for k in d if k.startswith('SQ_')))} "
                            f"--output-format csv -d <out> -o sq -- python3 bench.py --config {args.config} "
-                           f"--no-cpu --serving-jobs 0 --stream-buffers 0",
+                           f"--no-cpu --serving-jobs 0 --stream-buffers 0 --large-sets ''",
                            f"python3 bench.py --config {args.config} --prec {prec} --sq-from <out>"])
         p = os.path.join(PROFILES, f"sq_{args.config}_{prec}.json")
         json.dump(d, open(p, "w"), indent=1)

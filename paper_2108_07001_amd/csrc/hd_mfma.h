@@ -115,8 +115,10 @@ __global__ __launch_bounds__(256, 2) void hd_mfma(const HdArgs a, const MfmaOp<f
         float yy = 0.0f;
 #pragma unroll
         for (int d = 0; d < D; ++d) yy = __builtin_fmaf(y[g][d], y[g][d], yy);
-        // m = 126 makes the operand's shift 0: x_j = -c |y - x_j|^2
-        op[g].build(y[g], 16.0f / (yy + R2), 126, h);
+        // m = 126 makes the operand's shift 0: x_j = -c |y - x_j|^2. With this
+        // c every operand is in range for finite |y|^2 (c |y|^2 < 16, c <= 16 / R2
+        // <= 4096), so only an infinite or NaN |y|^2 counts as out of range.
+        op[g].build(y[g], 16.0f / (yy + R2), __FLT_MAX__, 126, h);
       }
       // pass 1: the largest metric of each sample over this lane's rows
       float mx[2] = {-__builtin_inff(), -__builtin_inff()};

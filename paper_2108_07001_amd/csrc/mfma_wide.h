@@ -109,6 +109,39 @@ struct WideSums {
   }
 };
 
+// Per-lane bit-side sums of the exact-size forms with one or two point tiles
+// (M = 32, 64). Each tile's 16 terms (element e = 4 x + y: y carries label
+// bits 0, 1 and x label bits 3, 4) are reduced to the two sides of each of
+// the four element bits and the tile's total -- row sums over y, column sums
+// over x, then pairs of those: 33 operations for 16 terms -- and the element
+// bits' sides accumulate over the tiles. The lane-half bit (label bit 2) and
+// the tile bit (label bit 5) come from the tiles' totals after the exchange
+// between the lane halves.
+template <bool ML>
+struct TileMarg {
+  float es[8];      // element bit eb, side b: es[2 eb + b]
+  float tt[2];      // totals of tiles 0 and 1
+  __device__ __forceinline__ void add(const float (&ev)[16], int t) {
+    float r[4], c[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) r[x] = cmb<ML>(cmb<ML>(ev[4 * x], ev[4 * x + 1]), cmb<ML>(ev[4 * x + 2], ev[4 * x + 3]));
+#pragma unroll
+    for (int y = 0; y < 4; ++y) c[y] = cmb<ML>(cmb<ML>(ev[y], ev[4 + y]), cmb<ML>(ev[8 + y], ev[12 + y]));
+    const float s[8] = {cmb<ML>(c[0], c[2]), cmb<ML>(c[1], c[3]), cmb<ML>(c[0], c[1]), cmb<ML>(c[2], c[3]),
+                        cmb<ML>(r[0], r[2]), cmb<ML>(r[1], r[3]), cmb<ML>(r[0], r[1]), cmb<ML>(r[2], r[3])};
+    const float tot = cmb<ML>(s[6], s[7]);
+    if (t == 0) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) es[i] = s[i];
+      tt[0] = tot;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) es[i] = cmb<ML>(es[i], s[i]);
+      tt[1] = tot;
+    }
+  }
+};
+
 // Exchange of a pair of per-group values between the lane halves: returns
 // (low-row half, high-row half) of the lane's own sample.
 __device__ __forceinline__ void own_halves(float a, float b, float& lo, float& hi) {
@@ -128,7 +161,7 @@ struct WideOperand {
   V B[NK];
   bool ovf;      // a sample-side value outside the operand range: exact path
 
-  __device__ __forceinline__ void build(const float (&y)[D], float c, int m, int h) {
+  __device__ __forceinline__ void build(const float (&y)[D], float c, float yy_lim, int m, int h) {
     const float K = Real<float>::shift(m);
     float yy = 0.0f;
 #pragma unroll
@@ -139,14 +172,20 @@ struct WideOperand {
     float w[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) w[d] = 2.0f * c * y[d];
-    ovf = !sample_features<D, BF>(w, -c, F);
+    (void)sample_features<D, BF>(w, -c, F);
     // S = K - c|y|^2, rounded to the operand type from below: lowering the
     // argument by more than one unit in the last place before rounding to
     // nearest keeps the rounded value <= S
     const float s0 = __builtin_fmaf(-c, yy, K);
     const float ulp = BF ? 0x1p-7f : 0x1p-10f;
     F[shift_slot(D, BF)] = (E)(s0 - __builtin_fabsf(s0) * ulp);
-    if (!BF) ovf |= !(__builtin_fabsf(s0) < 60000.0f);  // bfloat16 has the FP32 range
+    // half-precision range (bfloat16 has the FP32 range): every sample-side
+    // value below 60000 in magnitude. With c < 60000 (the caller's bound,
+    // c_lim), c|y|^2 < yy_lim = min(59000, 9e8 / c) / c implies |S| < 60000
+    // and |2 c y_d| <= 2 c |y| < 60000; one compare instead of one per value
+    // (stricter only for received points with a coordinate near |y| at
+    // extreme SNR, which then take the exact path). NaN fails it too.
+    ovf = BF ? false : !(yy < yy_lim);
     const uint32_t hmask = 0u - (uint32_t)h;
 #pragma unroll
     for (int kk = 0; kk < NK; ++kk) {
@@ -207,11 +246,13 @@ struct RawInput {
   uint32_t t;
   float z[D];
   __device__ __forceinline__ void fetch(const SampleParams& p, int64_t st, int j) {
-    const int64_t n = st * 32 + j;
-    const int64_t nc = n < p.N ? n : p.N - 1;
+    // 32-bit sample indices: a call holds fewer than 2^32 samples
+    const uint32_t n = (uint32_t)st * 32u + (uint32_t)j;
+    const uint32_t nlast = (uint32_t)p.N - 1u;
+    const uint32_t nc = n < nlast ? n : nlast;
     const uint32_t* __restrict__ txp = p.tx ? p.tx : reinterpret_cast<const uint32_t*>(p.in);
     t = txp[nc];
-    const float* __restrict__ in = p.in + nc * D;
+    const float* __restrict__ in = p.in + (uint64_t)nc * D;
 #pragma unroll
     for (int d = 0; d < D; ++d) z[d] = in[d];
   }
@@ -291,6 +332,16 @@ __device__ __forceinline__ void maxlog_direct(const float (&y)[D], const float* 
   }
 }
 
+// b if bit k of `word` is set, else a: v_bfi_b32 on the sign-extended bit,
+// two instructions (the compiler turns the same select written in C into a
+// shift, a compare and a conditional move).
+__device__ __forceinline__ float bit_select(float a, float b, int word, int k) {
+  const uint32_t msk = (uint32_t)__builtin_amdgcn_sbfe(word, k, 1);
+  uint32_t r;
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(msk), "v"(__float_as_uint(b)), "v"(__float_as_uint(a)));
+  return __uint_as_float(r);
+}
+
 // log2(1 + 2^x) in FP32 without overflow.
 __device__ __forceinline__ float softplus2(float x) {
   const float ax = __builtin_fabsf(x);
@@ -315,6 +366,7 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
   constexpr int NK = OP::NK;
   constexpr int NE = HALF ? 8 : 16;
   constexpr int NEB = HALF ? 3 : 4;       // element bits carrying label bits
+  constexpr bool MARG = MB == 5 || MB == 6;  // one or two point tiles: TileMarg
   extern __shared__ double acc_lds[];      // [waves][S][4], then the tables (TBL)
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
@@ -364,6 +416,9 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
     int nlisted = 0;
     unsigned int nflag = 0;                // samples flagged in those entries
     const SampleParams sp = sample_params(a, s);
+    // |y|^2 below which the half-precision operands are in range (see
+    // WideOperand::build); none at all if c itself is out of range
+    const float yy_lim = sp.c < 60000.0f ? __builtin_fminf(59000.0f, 9.0e8f / sp.c) / sp.c : -1.0f;
     const int64_t q0 = (wgid + ((((int64_t)s * rem) % wstride) & ~(int64_t)31)) % wstride;
     RawInput<D> inA, inB;
     if (q0 < npairs) {
@@ -382,8 +437,8 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
         inB.fetch(sp, 2 * qn + 1, j);
       }
       OP opA, opB;
-      opA.build(smA.y, sp.c, m, h);
-      opB.build(smB.y, sp.c, m, h);
+      opA.build(smA.y, sp.c, yy_lim, m, h);
+      opB.build(smB.y, sp.c, yy_lim, m, h);
 
       // the transmitted points' own terms: diagonals of the products whose A
       // rows are the groups' transmitted points
@@ -404,8 +459,11 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
       }
 
       WideSums<NE, LV, ML> sA, sB;
-      sA.init();
-      sB.init();
+      TileMarg<ML> mA, mB;
+      if constexpr (!MARG) {
+        sA.init();
+        sB.init();
+      }
       {
         V A[NK];
         const V* rp = rec_row<BF, HALF, NK>(tb.rec, 0, j, h);
@@ -422,10 +480,12 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
           float ev[NE];
 #pragma unroll
           for (int e = 0; e < NE; ++e) ev[e] = ML ? accA[e] : Real<float>::exp2(accA[e]);
-          sA.add(ev, t, ntb);
+          if constexpr (MARG) mA.add(ev, t);
+          else sA.add(ev, t, ntb);
 #pragma unroll
           for (int e = 0; e < NE; ++e) ev[e] = ML ? accB[e] : Real<float>::exp2(accB[e]);
-          sB.add(ev, t, ntb);
+          if constexpr (MARG) mB.add(ev, t);
+          else sB.add(ev, t, ntb);
         }
       }
       // own sample of this lane: group A in lanes 0..31, group B in 32..63
@@ -435,60 +495,86 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
       const int tl = h ? smB.tl : smA.tl;
       const bool ovf = h ? opB.ovf : opA.ovf;
 
-      // both row halves of the own sample
-      float r0[NE], r1[NE];
-#pragma unroll
-      for (int e = 0; e < NE; ++e) own_halves(sA.R[e], sB.R[e], r0[e], r1[e]);
       float side[2 * kMaxBits];
 #pragma unroll
       for (int i = 0; i < 2 * kMaxBits; ++i) side[i] = 0.f;
       float total;
-      {
-        float t0, t1;
-        own_halves(sA.tot, sB.tot, t0, t1);
-        total = cmb<ML>(t0, t1);
-      }
+      if constexpr (MARG) {
+        // the sample's element-bit sides and tile totals from both lane halves
 #pragma unroll
-      for (int l = 0; l < LV; ++l)
-        if (l < ntb) {
-          float x0, x1;
-          own_halves(sA.g0[l], sB.g0[l], x0, x1);
-          side[2 * (5 + l)] = cmb<ML>(x0, x1);
-          own_halves(sA.g1[l], sB.g1[l], x0, x1);
-          side[2 * (5 + l) + 1] = cmb<ML>(x0, x1);
+        for (int i = 0; i < 8; ++i) {
+          float lo, hi;
+          own_halves(mA.es[i], mB.es[i], lo, hi);
+          const int eb = i >> 1;
+          side[2 * (eb < 2 ? eb : eb + 1) + (i & 1)] = cmb<ML>(lo, hi);
         }
-      {
-        // label bit 2 is the row half
-        float c0 = r0[0], c1 = r1[0];
-#pragma unroll
-        for (int e = 1; e < NE; ++e) {
-          c0 = cmb<ML>(c0, r0[e]);
-          c1 = cmb<ML>(c1, r1[e]);
+        float t0lo, t0hi;
+        own_halves(mA.tt[0], mB.tt[0], t0lo, t0hi);
+        if constexpr (MB == 6) {
+          float t1lo, t1hi;
+          own_halves(mA.tt[1], mB.tt[1], t1lo, t1hi);
+          side[10] = cmb<ML>(t0lo, t0hi);      // label bit 5: the tile
+          side[11] = cmb<ML>(t1lo, t1hi);
+          side[4] = cmb<ML>(t0lo, t1lo);       // label bit 2: the lane half
+          side[5] = cmb<ML>(t0hi, t1hi);
+          total = cmb<ML>(side[10], side[11]);
+        } else {
+          side[4] = t0lo;
+          side[5] = t0hi;
+          total = cmb<ML>(t0lo, t0hi);
         }
-        side[4] = c0;
-        side[5] = c1;
-      }
-      {
-        // label bits 0, 1, 3 (, 4) are the element bits 0, 1, 2 (, 3)
-        float cur[NE];
+      } else {
+        // both row halves of the own sample
+        float r0[NE], r1[NE];
 #pragma unroll
-        for (int e = 0; e < NE; ++e) cur[e] = cmb<ML>(r0[e], r1[e]);
+        for (int e = 0; e < NE; ++e) own_halves(sA.R[e], sB.R[e], r0[e], r1[e]);
+        {
+          float t0, t1;
+          own_halves(sA.tot, sB.tot, t0, t1);
+          total = cmb<ML>(t0, t1);
+        }
 #pragma unroll
-        for (int eb = 0; eb < NEB; ++eb) {
-          const int half = NE >> (eb + 1);
-          float a0 = cur[0], a1 = cur[1];
+        for (int l = 0; l < LV; ++l)
+          if (l < ntb) {
+            float x0, x1;
+            own_halves(sA.g0[l], sB.g0[l], x0, x1);
+            side[2 * (5 + l)] = cmb<ML>(x0, x1);
+            own_halves(sA.g1[l], sB.g1[l], x0, x1);
+            side[2 * (5 + l) + 1] = cmb<ML>(x0, x1);
+          }
+        {
+          // label bit 2 is the row half
+          float c0 = r0[0], c1 = r1[0];
 #pragma unroll
-          for (int i = 1; i < NE / 2; ++i)
-            if (i < half) {
-              a0 = cmb<ML>(a0, cur[2 * i]);
-              a1 = cmb<ML>(a1, cur[2 * i + 1]);
-            }
+          for (int e = 1; e < NE; ++e) {
+            c0 = cmb<ML>(c0, r0[e]);
+            c1 = cmb<ML>(c1, r1[e]);
+          }
+          side[4] = c0;
+          side[5] = c1;
+        }
+        {
+          // label bits 0, 1, 3 (, 4) are the element bits 0, 1, 2 (, 3)
+          float cur[NE];
 #pragma unroll
-          for (int i = 0; i < NE / 2; ++i)
-            if (i < half) cur[i] = cmb<ML>(cur[2 * i], cur[2 * i + 1]);
-          const int k = eb < 2 ? eb : eb + 1;
-          side[2 * k] = a0;
-          side[2 * k + 1] = a1;
+          for (int e = 0; e < NE; ++e) cur[e] = cmb<ML>(r0[e], r1[e]);
+#pragma unroll
+          for (int eb = 0; eb < NEB; ++eb) {
+            const int half = NE >> (eb + 1);
+            float a0 = cur[0], a1 = cur[1];
+#pragma unroll
+            for (int i = 1; i < NE / 2; ++i)
+              if (i < half) {
+                a0 = cmb<ML>(a0, cur[2 * i]);
+                a1 = cmb<ML>(a1, cur[2 * i + 1]);
+              }
+#pragma unroll
+            for (int i = 0; i < NE / 2; ++i)
+              if (i < half) cur[i] = cmb<ML>(cur[2 * i], cur[2 * i + 1]);
+            const int k = eb < 2 ? eb : eb + 1;
+            side[2 * k] = a0;
+            side[2 * k + 1] = a1;
+          }
         }
       }
 
@@ -536,7 +622,7 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
       for (int i = 0; i < 2 * kMaxBits; ++i)
         if (i < 2 * m) smin = __builtin_fminf(smin, side[i]);
       const bool starved = ovf || !(smin >= thr);
-      float u = 0.f, v = 0.f;
+      float u = 0.f, v = -0.f;                 // -0 + x is x: no add for the first term
       if (live && !starved) {
         const float lam_tot = Real<float>::log2(total);
         float L[kMaxBits];
@@ -545,7 +631,7 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
           if (k < m) {
             const float l0 = Real<float>::log2(side[2 * k]), l1 = Real<float>::log2(side[2 * k + 1]);
             L[k] = Real<float>::ln2() * (l0 - l1);
-            if (tl >= 0) v += lam_tot - (((tl >> k) & 1) ? l1 : l0);
+            v += lam_tot - bit_select(l0, l1, tl, k);   // v is dropped unless tl >= 0
           }
         }
         if (lout) {
