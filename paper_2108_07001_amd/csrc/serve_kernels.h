@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void serve_tier1(const JobDesc* __restrict__ j
 }
 
 template <int D, bool BF, bool HALF>
-__global__ __launch_bounds__(256) void serve_tier2(const JobDesc* __restrict__ jobs, int njobs,
+__global__ __launch_bounds__(256, D <= 12 ? 2 : 1) void serve_tier2(const JobDesc* __restrict__ jobs, int njobs,
                                                    int64_t nitems) {
   typedef typename MfmaOp<BF>::vec V;
   typedef SampleTile<D, BF> ST;
