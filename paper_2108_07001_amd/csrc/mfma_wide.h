@@ -110,35 +110,50 @@ struct WideSums {
 };
 
 // Per-lane bit-side sums of the exact-size forms with one or two point tiles
-// (M = 32, 64). Each tile's 16 terms (element e = 4 x + y: y carries label
-// bits 0, 1 and x label bits 3, 4) are reduced to the two sides of each of
-// the four element bits and the tile's total -- row sums over y, column sums
-// over x, then pairs of those: 33 operations for 16 terms -- and the element
-// bits' sides accumulate over the tiles. The lane-half bit (label bit 2) and
-// the tile bit (label bit 5) come from the tiles' totals after the exchange
-// between the lane halves.
-template <bool ML>
+// (M = 32, 64). A tile's 16 terms (element e = 4 x + y: y carries label bits
+// 0, 1 and x label bits 3, 4) go into four row sums over y and four column
+// sums over x (24 operations), which accumulate over the tiles; at the end,
+// pairs of the row and column sums give the two sides of each of the four
+// element bits (8 operations). The lane-half bit (label bit 2) and the tile
+// bit (label bit 5) come from the tiles' totals after the exchange between
+// the lane halves; with two tiles each tile's total is taken from its own
+// row sums (3 operations), with one tile from its sides.
+template <bool ML, int NT>
 struct TileMarg {
-  float es[8];      // element bit eb, side b: es[2 eb + b]
-  float tt[2];      // totals of tiles 0 and 1
+  float r[4], c[4];     // row and column sums over the tiles
+  float tt[2];          // totals of tiles 0 and 1 (NT = 2)
+  float es[8];          // element bit eb, side b: es[2 eb + b] (after finish)
   __device__ __forceinline__ void add(const float (&ev)[16], int t) {
-    float r[4], c[4];
+    float rr[4], cc[4];
 #pragma unroll
-    for (int x = 0; x < 4; ++x) r[x] = cmb<ML>(cmb<ML>(ev[4 * x], ev[4 * x + 1]), cmb<ML>(ev[4 * x + 2], ev[4 * x + 3]));
+    for (int x = 0; x < 4; ++x) rr[x] = cmb<ML>(cmb<ML>(ev[4 * x], ev[4 * x + 1]), cmb<ML>(ev[4 * x + 2], ev[4 * x + 3]));
 #pragma unroll
-    for (int y = 0; y < 4; ++y) c[y] = cmb<ML>(cmb<ML>(ev[y], ev[4 + y]), cmb<ML>(ev[8 + y], ev[12 + y]));
-    const float s[8] = {cmb<ML>(c[0], c[2]), cmb<ML>(c[1], c[3]), cmb<ML>(c[0], c[1]), cmb<ML>(c[2], c[3]),
-                        cmb<ML>(r[0], r[2]), cmb<ML>(r[1], r[3]), cmb<ML>(r[0], r[1]), cmb<ML>(r[2], r[3])};
-    const float tot = cmb<ML>(s[6], s[7]);
+    for (int y = 0; y < 4; ++y) cc[y] = cmb<ML>(cmb<ML>(ev[y], ev[4 + y]), cmb<ML>(ev[8 + y], ev[12 + y]));
+    if (NT == 2) tt[t] = cmb<ML>(cmb<ML>(rr[0], rr[1]), cmb<ML>(rr[2], rr[3]));
     if (t == 0) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) es[i] = s[i];
-      tt[0] = tot;
+      for (int i = 0; i < 4; ++i) {
+        r[i] = rr[i];
+        c[i] = cc[i];
+      }
     } else {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) es[i] = cmb<ML>(es[i], s[i]);
-      tt[1] = tot;
+      for (int i = 0; i < 4; ++i) {
+        r[i] = cmb<ML>(r[i], rr[i]);
+        c[i] = cmb<ML>(c[i], cc[i]);
+      }
     }
+  }
+  __device__ __forceinline__ void finish() {
+    es[0] = cmb<ML>(c[0], c[2]);
+    es[1] = cmb<ML>(c[1], c[3]);
+    es[2] = cmb<ML>(c[0], c[1]);
+    es[3] = cmb<ML>(c[2], c[3]);
+    es[4] = cmb<ML>(r[0], r[2]);
+    es[5] = cmb<ML>(r[1], r[3]);
+    es[6] = cmb<ML>(r[0], r[1]);
+    es[7] = cmb<ML>(r[2], r[3]);
+    if (NT == 1) tt[0] = cmb<ML>(es[6], es[7]);
   }
 };
 
@@ -459,7 +474,7 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
       }
 
       WideSums<NE, LV, ML> sA, sB;
-      TileMarg<ML> mA, mB;
+      TileMarg<ML, (MB == 6 ? 2 : 1)> mA, mB;
       if constexpr (!MARG) {
         sA.init();
         sB.init();
@@ -500,6 +515,8 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
       for (int i = 0; i < 2 * kMaxBits; ++i) side[i] = 0.f;
       float total;
       if constexpr (MARG) {
+        mA.finish();
+        mB.finish();
         // the sample's element-bit sides and tile totals from both lane halves
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
