@@ -114,12 +114,12 @@ def counters_from(out_dir: str, kernel: str) -> dict:
     return {k: sum(v.values()) / len(v) for k, v in acc.items()}
 
 
-def stored_issue(workload: str, prec: str, kernel_ms: float):
+def stored_issue(workload: str, prec: str, kernel_ms: float, tier: int = 1):
     """VALU issue of the main kernel from the committed SQ counter summary:
     instructions per launch and the fraction of the issue limit (one wave64
     VALU instruction per SIMD every 4 cycles) they take at the measured launch
     time; None when there is no summary or the sources changed since."""
-    p = os.path.join(PROFILES, f"sq_{workload}_{prec}.json")
+    p = os.path.join(PROFILES, f"sq_{profile_suffix(workload, prec, tier)}.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
@@ -132,20 +132,37 @@ def stored_issue(workload: str, prec: str, kernel_ms: float):
             "note": "exp2/log2 occupy the SIMD for two issue slots; they are counted once here"}
 
 
-def stored_traffic(workload: str, prec: str):
+def stored_traffic(workload: str, prec: str, tier: int = 1):
     """HBM bytes per launch of the main kernel from the committed counter
     summary (FETCH_SIZE / WRITE_SIZE scaled by a plain copy's readings), or
     None when there is none for this workload or the sources changed since."""
-    p = os.path.join(PROFILES, f"traffic_{workload}_{prec}.json")
+    p = os.path.join(PROFILES, f"traffic_{profile_suffix(workload, prec, tier)}.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
     return d["bytes_per_launch"] if d.get("source_hash") == source_hash() else None
 
 
-# Name of the exact first tier as the profiler prints it (template arguments
-# D, bfloat16 operands, tables in LDS, exact-size form log2 M or 0, max-log).
-FIRST_TIER_KERNEL = "demap_mfma_w<{D}, {BF}, true, {MB}, false>"
+def kernel_name(M: int, D: int, prec: str, tier: int) -> str:
+    """A matrix-core demapping kernel as the profiler prints it. First tier:
+    demap_mfma_w<D, bfloat16 operands, tables in LDS, exact-size log2 M or 0,
+    max-log>; second tier: demap_mfma_t2<D, bfloat16, 16-point tiles, tables
+    in LDS>. The tables go to LDS when they take at most 40 KB (labels, FP32
+    coordinates and the point records, as the library lays them out)."""
+    bf = prec == "bf16x3"
+    feat = 6 * D + 6 if bf else 3 * D + 3
+    nk = (feat + 1 + 15) // 16
+    tbl = M * 4 + M * D * 4 + 16 + M * nk * 32 <= 40 * 1024
+    b = "true" if bf else "false"
+    if tier == 1:
+        mb = {16: 4, 32: 5, 64: 6}.get(M, 0)
+        return f"demap_mfma_w<{D}, {b}, {'true' if (tbl or mb) else 'false'}, {mb}, false>"
+    half = M == 16
+    return f"demap_mfma_t2<{D}, {b}, {'true' if half else 'false'}, {'true' if (half or tbl) else 'false'}>"
+
+
+def profile_suffix(config: str, prec: str, tier: int) -> str:
+    return f"{config}_{prec}" + ("_t2" if tier == 2 else "")
 
 
 def inputs_config(name: str) -> dict:
@@ -395,6 +412,10 @@ def large_sets(ctx, names, steps: int) -> dict:
                       "step_trans_frac": trans / (ms * 1e-3) / TRANS_PEAK,
                       "second_tier_items": int(ctx.last_recomputed()), "exact_path_items": int(ctx.last_exact()),
                       "mi_gmi_first_last": [float(x) for x in stats.cpu().numpy()[[0, -1], :2].ravel()]}
+            if p != "fp32":
+                # counter summaries of this build's first tier, where committed
+                res[p]["first_tier_traffic_bytes"] = stored_traffic(name, p)
+                res[p]["first_tier_valu_issue"] = stored_issue(name, p, kstep)
             log(f"{name} {p}: {ms:.2f} ms/step (first tier {kstep:.2f} ms), second tier "
                 f"{res[p]['second_tier_items']} items, exact {res[p]['exact_path_items']}")
         for p in ("fp16x3", "bf16x3"):
@@ -436,6 +457,11 @@ def main():
                     help="timed steps per matrix-core form of each large sweep (the plain FP32 kernel: 1)")
     ap.add_argument("--roofs", action="store_true",
                     help="only measure the unit rates (air_measure_roofs) and print them as JSON")
+    ap.add_argument("--tier", type=int, default=1, choices=(1, 2),
+                    help="--traffic-from / --sq-from: the first tier's kernel or the second tier's")
+    ap.add_argument("--profile-args", default="",
+                    help="--traffic-from / --sq-from: further bench.py arguments of the profiled runs, "
+                         "recorded in the summary's commands")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device-to-device copy of 1 GiB (3 times), the "
                          "reference for scaling hardware byte counters")
@@ -443,32 +469,32 @@ def main():
     if args.traffic_from:
         prec = args.prec or "fp16x3"
         w0 = inputs_config(args.config)
-        kern = FIRST_TIER_KERNEL.format(D=w0["D"], BF="true" if prec == "bf16x3" else "false",
-                                        MB={16: 4, 32: 5, 64: 6}.get(w0["M"], 0))
+        kern = kernel_name(w0["M"], w0["D"], prec, args.tier)
         run = (f"python3 bench.py --config {args.config} --no-cpu --serving-jobs 0 --stream-buffers 0 "
-               f"--large-sets ''")
+               f"--large-sets '' {args.profile_args}").strip()
         cmds = [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/f -o f -- {run}",
                 f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/w -o w -- {run}",
                 "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/cf -o cf -- python3 bench.py --copy-probe",
                 "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/cw -o cw -- python3 bench.py --copy-probe",
-                f"python3 bench.py --config {args.config} --prec {prec} --traffic-from <out>"]
+                f"python3 bench.py --config {args.config} --prec {prec} --tier {args.tier} --traffic-from <out>"]
         d = traffic_from(args.traffic_from, args.config, prec, kern, cmds)
-        p = os.path.join(PROFILES, f"traffic_{args.config}_{prec}.json")
+        p = os.path.join(PROFILES, f"traffic_{profile_suffix(args.config, prec, args.tier)}.json")
         json.dump(d, open(p, "w"), indent=1)
         print(json.dumps({"wrote": p, "bytes_per_launch": d["bytes_per_launch"]}))
         return
     if args.sq_from:
         prec = args.prec or "fp16x3"
         w0 = inputs_config(args.config)
-        kern = FIRST_TIER_KERNEL.format(D=w0["D"], BF="true" if prec == "bf16x3" else "false",
-                                        MB={16: 4, 32: 5, 64: 6}.get(w0["M"], 0))
+        kern = kernel_name(w0["M"], w0["D"], prec, args.tier)
         d = counters_from(args.sq_from, kern)
+        run = (f"python3 bench.py --config {args.config} --no-cpu --serving-jobs 0 --stream-buffers 0 "
+               f"--large-sets '' {args.profile_args}").strip()
         d.update(kernel=kern, workload=args.config, prec=prec, source_hash=source_hash(),
-                 commands=[f"rocprofv3 --pmc {' '.join(sorted(k for k in d if k.startswith('SQ_')))} "
-                           f"--output-format csv -d <out> -o sq -- python3 bench.py --config {args.config} "
-                           f"--no-cpu --serving-jobs 0 --stream-buffers 0 --large-sets ''",
-                           f"python3 bench.py --config {args.config} --prec {prec} --sq-from <out>"])
-        p = os.path.join(PROFILES, f"sq_{args.config}_{prec}.json")
+                 commands=[f"rocprofv3 --pmc {' '.join(sorted(k for k in d if not k[0].islower()))} "
+                           f"--output-format csv -d <out> -o sq -- {run}",
+                           f"python3 bench.py --config {args.config} --prec {prec} --tier {args.tier} "
+                           f"--sq-from <out>"])
+        p = os.path.join(PROFILES, f"sq_{profile_suffix(args.config, prec, args.tier)}.json")
         json.dump(d, open(p, "w"), indent=1)
         print(json.dumps({"wrote": p}))
         return
