@@ -439,8 +439,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true",
                     help="skip timing the plain FP32 kernel beside the matrix-core form")
-    ap.add_argument("--serving-jobs", type=int, default=4000,
-                    help="jobs of the Poisson serving mix to replay (0: skip; full mix: 20000)")
+    ap.add_argument("--serving-jobs", type=int, default=20000,
+                    help="jobs of the Poisson serving mix to replay (the full mix: 20000, 10 s per pass; 0: skip)")
     ap.add_argument("--stream-buffers", type=int, default=12,
                     help="2^20-symbol M-QAM buffers per format streamed from host memory (0: skip)")
     ap.add_argument("--traffic-from", default=None,

@@ -47,9 +47,26 @@ def test_hard_sweep_matches_oracle(ctx, name, N):
         sf = np.float32(math.sqrt(oracle.sigma2(w.X, w.snr_db[s])))
         Y = (sf * z32 + w.X[w.tx].astype(np.float32)).astype(np.float32)
         ndiff += _check_decisions(w.X, Y, got[s], ref["decided"][s])
+    got_counts = counts.cpu().numpy().astype(np.uint64)
+    # the counts always match the kernel's own decisions (counted here on the host) ...
+    np.testing.assert_array_equal(got_counts, _counts_of(w.labels, w.tx, got))
+    # ... and the oracle's counts whenever no decision differs at a tie
     if ndiff == 0:
-        np.testing.assert_array_equal(counts.cpu().numpy().astype(np.uint64), ref["counts"])
+        np.testing.assert_array_equal(got_counts, ref["counts"])
     c.close()
+
+
+def _counts_of(labels, tx, decided):
+    """[symbol errors, bit errors] per row of `decided` (S x N point indices)."""
+    lab = np.asarray(labels, dtype=np.uint32)
+    t = lab[np.asarray(tx)]
+    out = np.zeros((decided.shape[0], 2), dtype=np.uint64)
+    for s in range(decided.shape[0]):
+        d = lab[decided[s]]
+        out[s, 0] = np.count_nonzero(decided[s] != np.asarray(tx))
+        x = (d ^ t).astype(np.uint32)
+        out[s, 1] = int(np.unpackbits(x.view(np.uint8)).sum())
+    return out
 
 
 def test_hard_decide_given_block(ctx):
