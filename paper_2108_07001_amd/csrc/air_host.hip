@@ -226,9 +226,11 @@ double from_bf16_bits(uint16_t b) {
 // operand bits, q = |x|^2, every part rounded to nearest even:
 //  half precision: [x_hi | x_lo | x_hi | q_hi, q_lo, q_hi | 1 | 0...],
 //    hi = round(v), lo = round(v - hi);
-//  bfloat16: [x_hi | x_mid | x_lo | x_hi | x_mid | x_hi |
-//             q_hi, q_mid, q_lo, q_hi, q_mid, q_hi | 1 | 0...],
-//    hi = round(v), mid = round(v - hi), lo = round(v - hi - mid).
+//  bfloat16, D <= 4: [x_hi | x_mid | x_lo | x_hi | x_mid | x_hi |
+//             q_hi, q_mid, q_lo, q_hi, q_mid, q_hi | 1 | 0...];
+//  bfloat16, D > 4: [x_hi | q_hi, q_mid, q_lo | 1 | x_mid | x_lo | 0...]
+//    (each chunk taken by up to three products, one per split level of the
+//    sample side), hi = round(v), mid = round(v - hi), lo = round(v - hi - mid).
 // The 1 multiplies the sample side's per-sample shift.
 void point_record(const double* x, int D, bool bf, uint16_t* out) {
   const int kp = 16 * mfma_nk(D, bf);
@@ -257,24 +259,37 @@ void point_record(const double* x, int D, bool bf, uint16_t* out) {
       mid = cv(r);
       lo = cv(r - back(mid));
     };
-    for (int d = 0; d < D; ++d) {
-      uint16_t hi, mid, lo;
-      split3(x[d], hi, mid, lo);
-      out[d] = hi;
-      out[D + d] = mid;
-      out[2 * D + d] = lo;
-      out[3 * D + d] = hi;
-      out[4 * D + d] = mid;
-      out[5 * D + d] = hi;
-    }
     uint16_t qh, qm, ql;
     split3(q, qh, qm, ql);
-    out[6 * D] = qh;
-    out[6 * D + 1] = qm;
-    out[6 * D + 2] = ql;
-    out[6 * D + 3] = qh;
-    out[6 * D + 4] = qm;
-    out[6 * D + 5] = qh;
+    if (bf_shared(D)) {
+      for (int d = 0; d < D; ++d) {
+        uint16_t hi, mid, lo;
+        split3(x[d], hi, mid, lo);
+        out[d] = hi;
+        out[D + 4 + d] = mid;
+        out[2 * D + 4 + d] = lo;
+      }
+      out[D] = qh;
+      out[D + 1] = qm;
+      out[D + 2] = ql;
+    } else {
+      for (int d = 0; d < D; ++d) {
+        uint16_t hi, mid, lo;
+        split3(x[d], hi, mid, lo);
+        out[d] = hi;
+        out[D + d] = mid;
+        out[2 * D + d] = lo;
+        out[3 * D + d] = hi;
+        out[4 * D + d] = mid;
+        out[5 * D + d] = hi;
+      }
+      out[6 * D] = qh;
+      out[6 * D + 1] = qm;
+      out[6 * D + 2] = ql;
+      out[6 * D + 3] = qh;
+      out[6 * D + 4] = qm;
+      out[6 * D + 5] = qh;
+    }
   }
   out[shift_slot(D, bf)] = cv(1.0);
 }

@@ -63,11 +63,68 @@ typedef float float16_t __attribute__((ext_vector_type(16)));
 
 constexpr int kTileLevels = kMaxBits - 5;   // label bits carried by the point-tile index
 
-// K slots used by a constellation of dimension D (3 D + 3 feature slots in
-// half precision, 6 D + 6 in bfloat16, and one slot for a per-sample shift),
-// padded to whole products.
-__host__ __device__ constexpr int shift_slot(int D, bool bf) { return bf ? 6 * D + 6 : 3 * D + 3; }
-__host__ __device__ constexpr int mfma_nk(int D, bool bf = false) { return (shift_slot(D, bf) + 1 + 15) / 16; }
+// K slots of a point record, padded to whole 16-slot chunks (q = |x|^2):
+//  half precision: [x_hi | x_lo | x_hi | q_hi, q_lo, q_hi | 1], one product
+//    per chunk, the sample side pairing slot for slot;
+//  bfloat16, D <= 4: [x_hi | x_mid | x_lo | x_hi | x_mid | x_hi |
+//    q_hi, q_mid, q_lo, q_hi, q_mid, q_hi | 1], likewise one product per
+//    chunk;
+//  bfloat16, D > 4 (shared chunks): [x_hi | q_hi, q_mid, q_lo | 1 | x_mid |
+//    x_lo], each chunk taken by up to three products, one per split level of
+//    the sample side (hi, mid, lo), which pairs that level with the chunk's
+//    point parts whose levels leave a sum of at most 2.
+// Either bfloat16 form keeps the six products hi·hi, hi·mid, mid·hi, hi·lo,
+// lo·hi, mid·mid (the shift's 1 pairs with the hi level only). Sharing chunks
+// makes the records as small as the half-precision ones, which matters where
+// the run-time-M kernels stream them from L2; at D <= 4 the records fit one
+// or two chunks either way and the extra product per chunk costs more.
+__host__ __device__ constexpr bool bf_shared(int D) { return D > 4; }
+__host__ __device__ constexpr int shift_slot(int D, bool bf) {
+  return !bf ? 3 * D + 3 : bf_shared(D) ? D + 3 : 6 * D + 6;
+}
+__host__ __device__ constexpr int mfma_nk(int D, bool bf = false) {
+  return (bf && !bf_shared(D) ? 6 * D + 7 + 15 : 3 * D + 4 + 15) / 16;
+}
+
+// Split level of the point part in bfloat16 slot s: 0 hi, 1 mid, 2 lo (the
+// shift's 1 counts as lo), 3 for padding (pairs with nothing).
+__host__ __device__ constexpr int bf_slot_level(int D, int s) {
+  return s < D ? 0 : s < D + 3 ? s - D : s == D + 3 ? 2 : s < 2 * D + 4 ? 1 : s < 3 * D + 4 ? 2 : 3;
+}
+
+// Products of the K chain: one per chunk, except in the shared-chunk
+// bfloat16 form, where a chunk takes as many as the sample levels its highest
+// point part pairs with (chunk by chunk, levels in increasing order).
+template <int D, bool BF>
+struct KPlan {
+  static constexpr int NK = mfma_nk(D, BF);      // record chunks
+  static constexpr int levels(int c) {
+    if (!BF || !bf_shared(D)) return 1;
+    int lo = 3;
+    for (int s = 16 * c; s < 16 * c + 16; ++s) lo = bf_slot_level(D, s) < lo ? bf_slot_level(D, s) : lo;
+    return 3 - lo;
+  }
+  static constexpr int count() {
+    int n = 0;
+    for (int c = 0; c < NK; ++c) n += levels(c);
+    return n;
+  }
+  static constexpr int NP = count();             // products
+  static constexpr int chunk(int p) {
+    for (int c = 0; c < NK; ++c) {
+      if (p < levels(c)) return c;
+      p -= levels(c);
+    }
+    return 0;
+  }
+  static constexpr int level(int p) {
+    for (int c = 0; c < NK; ++c) {
+      if (p < levels(c)) return p;
+      p -= levels(c);
+    }
+    return 0;
+  }
+};
 
 template <bool BF> struct MfmaOp;
 template <> struct MfmaOp<false> {
@@ -112,13 +169,29 @@ __device__ __forceinline__ void split3_bf16(float v0, float v1, __bf16 (&hi)[2],
   lo[1] = l.y;
 }
 
-// Sample-side features of the K slots (all but the shift slot) from
-// w = 2 c y and nc = -c, in the order of the point records; F must be zeroed.
-// Returns false when a value leaves the half-precision range (bfloat16 has
-// the FP32 range).
+// Sample-side operands of this lane's K half (h) for the products of the K
+// chain, from w = 2 c y, nc = -c and the value S of the shift slot (0 when
+// the accumulator carries the shift), in the order of the point records.
+// The halves are selected on packed 32-bit words so that the choice never
+// becomes an index. Returns false when a value leaves the half-precision
+// range (bfloat16 has the FP32 range).
 template <int D, bool BF>
-__device__ __forceinline__ bool sample_features(const float (&w)[D], float nc, typename MfmaOp<BF>::elem* F) {
-  if constexpr (BF) {
+__device__ __forceinline__ bool sample_operands(const float (&w)[D], float nc, float S, int h,
+                                                typename MfmaOp<BF>::vec (&B)[KPlan<D, BF>::NP]) {
+  typedef typename MfmaOp<BF>::elem E;
+  typedef KPlan<D, BF> P;
+  const uint32_t hmask = 0u - (uint32_t)h;
+  auto pack = [hmask](E a0, E a1, E b0, E b1) {
+    E p0[2] = {a0, a1}, p1[2] = {b0, b1};
+    uint32_t w0, w1;
+    __builtin_memcpy(&w0, p0, 4);
+    __builtin_memcpy(&w1, p1, 4);
+    return (w0 & ~hmask) | (w1 & hmask);
+  };
+  if constexpr (BF && !bf_shared(D)) {
+    E F[16 * P::NK];
+#pragma unroll
+    for (int k = 0; k < 16 * P::NK; ++k) F[k] = (E)0.0f;
 #pragma unroll
     for (int d = 0; d < D; d += 2) {
       const int d1 = d + 1 < D ? d + 1 : d;
@@ -143,12 +216,67 @@ __device__ __forceinline__ bool sample_features(const float (&w)[D], float nc, t
     F[6 * D + 3] = mid[0];
     F[6 * D + 4] = mid[0];
     F[6 * D + 5] = lo[0];
+    F[shift_slot(D, true)] = (E)S;
+#pragma unroll
+    for (int kk = 0; kk < P::NK; ++kk) {
+      uint32_t wd[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        wd[q] = pack(F[16 * kk + 2 * q], F[16 * kk + 2 * q + 1], F[16 * kk + 8 + 2 * q], F[16 * kk + 9 + 2 * q]);
+      __builtin_memcpy(&B[kk], wd, 16);
+    }
+    return true;
+  } else if constexpr (BF) {
+    // shared chunks: hi, mid, lo of every w_d and of nc
+    E wl[3][D], nl[3];
+#pragma unroll
+    for (int d = 0; d < D; d += 2) {
+      const int d1 = d + 1 < D ? d + 1 : d;
+      __bf16 hi[2], mid[2], lo[2];
+      split3_bf16(w[d], d + 1 < D ? w[d1] : 0.0f, hi, mid, lo);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        if (d + i < D) {
+          wl[0][d + i] = hi[i];
+          wl[1][d + i] = mid[i];
+          wl[2][d + i] = lo[i];
+        }
+    }
+    {
+      __bf16 hi[2], mid[2], lo[2];
+      split3_bf16(nc, 0.0f, hi, mid, lo);
+      nl[0] = hi[0];
+      nl[1] = mid[0];
+      nl[2] = lo[0];
+    }
+    const E sb = (E)S;
+    // the sample value that slot s pairs with at level l (0 if none)
+    auto val = [&](int s, int l) -> E {
+      if (bf_slot_level(D, s) + l > 2) return (E)0.0f;
+      if (s < D) return wl[l][s];
+      if (s < D + 3) return nl[l];
+      if (s == D + 3) return sb;
+      if (s < 2 * D + 4) return wl[l][s - D - 4];
+      return wl[l][s - 2 * D - 4];
+    };
+#pragma unroll
+    for (int p = 0; p < P::NP; ++p) {
+      const int c0 = 16 * P::chunk(p), l = P::level(p);
+      uint32_t wd[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        wd[q] = pack(val(c0 + 2 * q, l), val(c0 + 2 * q + 1, l), val(c0 + 8 + 2 * q, l), val(c0 + 9 + 2 * q, l));
+      __builtin_memcpy(&B[p], wd, 16);
+    }
     return true;
   } else {
     // half precision: two dimensions at a time with the packed conversion
     // (round to nearest even), which writes whole registers
     typedef _Float16 h2 __attribute__((ext_vector_type(2)));
     typedef float f2 __attribute__((ext_vector_type(2)));
+    E F[16 * P::NK];
+#pragma unroll
+    for (int k = 0; k < 16 * P::NK; ++k) F[k] = (E)0.0f;
     bool ok = __builtin_fabsf(nc) < 60000.0f;
 #pragma unroll
     for (int d = 0; d < D; d += 2) {
@@ -172,6 +300,15 @@ __device__ __forceinline__ bool sample_features(const float (&w)[D], float nc, t
     F[3 * D] = hi;
     F[3 * D + 1] = hi;
     F[3 * D + 2] = lo;
+    F[shift_slot(D, false)] = (E)S;
+#pragma unroll
+    for (int kk = 0; kk < P::NK; ++kk) {
+      uint32_t wd[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        wd[q] = pack(F[16 * kk + 2 * q], F[16 * kk + 2 * q + 1], F[16 * kk + 8 + 2 * q], F[16 * kk + 9 + 2 * q]);
+      __builtin_memcpy(&B[kk], wd, 16);
+    }
     return ok;
   }
 }
@@ -271,13 +408,13 @@ template <int D, bool BF>
 struct SampleTile {
   typedef typename MfmaOp<BF>::vec V;
   typedef typename MfmaOp<BF>::elem E;
-  static constexpr int NK = mfma_nk(D, BF);
-  static constexpr int KP = 16 * NK;
+  static constexpr int NK = KPlan<D, BF>::NK;    // record chunks
+  static constexpr int NP = KPlan<D, BF>::NP;    // products
   int64_t n;
   bool valid, live;
   int tl, tq;          // label of the transmitted point (-1 none, -2 invalid); in-bounds row
   bool ovf;            // sample side outside the f16 range: exact path
-  V B[NK];
+  V B[NP];
   float16_t cinit;
 
   __device__ __forceinline__ void setup(const SampleParams& p, int64_t st, int j, int h,
@@ -312,39 +449,21 @@ struct SampleTile {
       y[d] = (p.sweep && live) ? __builtin_fmaf(sigma, zi, ti.xt[d]) : zi;
       yy = __builtin_fmaf(y[d], y[d], yy);
     }
-    // sample-side features; each lane takes its half of every 16-slot group,
-    // selected on packed 32-bit words so the choice never becomes an index
-    E F[KP];
-#pragma unroll
-    for (int k = 0; k < KP; ++k) F[k] = (E)0.0f;
+    // sample-side operands of this lane's K half (the shift is in the
+    // accumulator input)
     float w[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) w[d] = 2.0f * c * y[d];
-    ovf = !sample_features<D, BF>(w, -c, F);
-    const uint32_t hmask = 0u - (uint32_t)h;
-#pragma unroll
-    for (int kk = 0; kk < NK; ++kk) {
-      uint32_t wd[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        uint32_t w0, w1;
-        E p0[2] = {F[16 * kk + 2 * q], F[16 * kk + 2 * q + 1]};
-        E p1[2] = {F[16 * kk + 8 + 2 * q], F[16 * kk + 8 + 2 * q + 1]};
-        __builtin_memcpy(&w0, p0, 4);
-        __builtin_memcpy(&w1, p1, 4);
-        wd[q] = (w0 & ~hmask) | (w1 & hmask);
-      }
-      __builtin_memcpy(&B[kk], wd, 16);
-    }
+    ovf = !sample_operands<D, BF>(w, -c, 0.0f, h, B);
     const float c0 = __builtin_fmaf(-c, yy, K);
 #pragma unroll
     for (int e = 0; e < 16; ++e) cinit[e] = c0;
   }
 
   __device__ __forceinline__ float16_t product(const V (&A)[NK]) const {
-    float16_t acc = MfmaOp<BF>::mma(A[0], B[0], cinit);
+    float16_t acc = MfmaOp<BF>::mma(A[KPlan<D, BF>::chunk(0)], B[0], cinit);
 #pragma unroll
-    for (int kk = 1; kk < NK; ++kk) acc = MfmaOp<BF>::mma(A[kk], B[kk], acc);
+    for (int p = 1; p < NP; ++p) acc = MfmaOp<BF>::mma(A[KPlan<D, BF>::chunk(p)], B[p], acc);
     return acc;
   }
 

@@ -171,9 +171,9 @@ template <int D, bool BF>
 struct WideOperand {
   typedef typename MfmaOp<BF>::vec V;
   typedef typename MfmaOp<BF>::elem E;
-  static constexpr int NK = mfma_nk(D, BF);
-  static constexpr int KP = 16 * NK;
-  V B[NK];
+  static constexpr int NK = KPlan<D, BF>::NK;    // record chunks
+  static constexpr int NP = KPlan<D, BF>::NP;    // products
+  V B[NP];
   bool ovf;      // a sample-side value outside the operand range: exact path
 
   __device__ __forceinline__ void build(const float (&y)[D], float c, float yy_lim, int m, int h) {
@@ -181,19 +181,15 @@ struct WideOperand {
     float yy = 0.0f;
 #pragma unroll
     for (int d = 0; d < D; ++d) yy = __builtin_fmaf(y[d], y[d], yy);
-    E F[KP];
-#pragma unroll
-    for (int k = 0; k < KP; ++k) F[k] = (E)0.0f;
     float w[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) w[d] = 2.0f * c * y[d];
-    (void)sample_features<D, BF>(w, -c, F);
     // S = K - c|y|^2, rounded to the operand type from below: lowering the
     // argument by more than one unit in the last place before rounding to
     // nearest keeps the rounded value <= S
     const float s0 = __builtin_fmaf(-c, yy, K);
     const float ulp = BF ? 0x1p-7f : 0x1p-10f;
-    F[shift_slot(D, BF)] = (E)(s0 - __builtin_fabsf(s0) * ulp);
+    (void)sample_operands<D, BF>(w, -c, s0 - __builtin_fabsf(s0) * ulp, h, B);
     // half-precision range (bfloat16 has the FP32 range): every sample-side
     // value below 60000 in magnitude. With c < 60000 (the caller's bound,
     // c_lim), c|y|^2 < yy_lim = min(59000, 9e8 / c) / c implies |S| < 60000
@@ -201,28 +197,13 @@ struct WideOperand {
     // (stricter only for received points with a coordinate near |y| at
     // extreme SNR, which then take the exact path). NaN fails it too.
     ovf = BF ? false : !(yy < yy_lim);
-    const uint32_t hmask = 0u - (uint32_t)h;
-#pragma unroll
-    for (int kk = 0; kk < NK; ++kk) {
-      uint32_t wd[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        uint32_t w0, w1;
-        E p0[2] = {F[16 * kk + 2 * q], F[16 * kk + 2 * q + 1]};
-        E p1[2] = {F[16 * kk + 8 + 2 * q], F[16 * kk + 8 + 2 * q + 1]};
-        __builtin_memcpy(&w0, p0, 4);
-        __builtin_memcpy(&w1, p1, 4);
-        wd[q] = (w0 & ~hmask) | (w1 & hmask);
-      }
-      __builtin_memcpy(&B[kk], wd, 16);
-    }
   }
 
   __device__ __forceinline__ float16_t product(const V (&A)[NK]) const {
     const float16_t zero = {};
-    float16_t acc = MfmaOp<BF>::mma(A[0], B[0], zero);
+    float16_t acc = MfmaOp<BF>::mma(A[KPlan<D, BF>::chunk(0)], B[0], zero);
 #pragma unroll
-    for (int kk = 1; kk < NK; ++kk) acc = MfmaOp<BF>::mma(A[kk], B[kk], acc);
+    for (int p = 1; p < NP; ++p) acc = MfmaOp<BF>::mma(A[KPlan<D, BF>::chunk(p)], B[p], acc);
     return acc;
   }
 };
