@@ -223,15 +223,14 @@ double from_bf16_bits(uint16_t b) {
 }
 
 // Point side of the matrix-core K slots for one point x (length D), as
-// operand bits, q = |x|^2, every part rounded to nearest even:
-//  half precision: [x_hi | x_lo | x_hi | q_hi, q_lo, q_hi | 1 | 0...],
-//    hi = round(v), lo = round(v - hi);
-//  bfloat16, D <= 4: [x_hi | x_mid | x_lo | x_hi | x_mid | x_hi |
-//             q_hi, q_mid, q_lo, q_hi, q_mid, q_hi | 1 | 0...];
-//  bfloat16, D > 4: [x_hi | q_hi, q_mid, q_lo | 1 | x_mid | x_lo | 0...]
-//    (each chunk taken by up to three products, one per split level of the
-//    sample side), hi = round(v), mid = round(v - hi), lo = round(v - hi - mid).
-// The 1 multiplies the sample side's per-sample shift.
+// operand bits, q = |x|^2, every part rounded to nearest even (hi = round(v),
+// lo = round(v - hi); bfloat16: mid = round(v - hi), lo = round(v - hi - mid)):
+//  slot for slot, half precision: [x_hi | x_lo | x_hi | q_hi, q_lo, q_hi | 1],
+//    bfloat16: [x_hi | x_mid | x_lo | x_hi | x_mid | x_hi |
+//               q_hi, q_mid, q_lo, q_hi, q_mid, q_hi | 1];
+//  shared chunks, half precision: [x_hi | q_hi, q_lo | 1 | x_lo],
+//    bfloat16: [x_hi | q_hi, q_mid, q_lo | 1 | x_mid | x_lo];
+// then zeros to whole chunks. The 1 multiplies the sample side's shift.
 void point_record(const double* x, int D, bool bf, uint16_t* out) {
   const int kp = 16 * mfma_nk(D, bf);
   auto cv = [bf](double v) { return bf ? to_bf16_bits(v) : to_f16_bits(v); };
@@ -239,57 +238,61 @@ void point_record(const double* x, int D, bool bf, uint16_t* out) {
   for (int k = 0; k < kp; ++k) out[k] = 0;
   double q = 0.0;
   for (int d = 0; d < D; ++d) q += x[d] * x[d];
-  if (!bf) {
-    for (int d = 0; d < D; ++d) {
-      const uint16_t hi = cv(x[d]);
-      const uint16_t lo = cv(x[d] - back(hi));
-      out[d] = hi;
-      out[D + d] = lo;
-      out[2 * D + d] = hi;
-    }
-    const uint16_t qh = cv(q);
-    const uint16_t ql = cv(q - back(qh));
-    out[3 * D] = qh;
-    out[3 * D + 1] = ql;
-    out[3 * D + 2] = qh;
-  } else {
-    auto split3 = [&](double v, uint16_t& hi, uint16_t& mid, uint16_t& lo) {
-      hi = cv(v);
-      const double r = v - back(hi);
-      mid = cv(r);
-      lo = cv(r - back(mid));
-    };
-    uint16_t qh, qm, ql;
-    split3(q, qh, qm, ql);
-    if (bf_shared(D)) {
-      for (int d = 0; d < D; ++d) {
-        uint16_t hi, mid, lo;
-        split3(x[d], hi, mid, lo);
-        out[d] = hi;
-        out[D + 4 + d] = mid;
-        out[2 * D + 4 + d] = lo;
-      }
-      out[D] = qh;
-      out[D + 1] = qm;
-      out[D + 2] = ql;
+  // parts[level]: hi, (mid,) lo
+  auto split = [&](double v, uint16_t* parts) {
+    parts[0] = cv(v);
+    const double r = v - back(parts[0]);
+    if (bf) {
+      parts[1] = cv(r);
+      parts[2] = cv(r - back(parts[1]));
     } else {
-      for (int d = 0; d < D; ++d) {
-        uint16_t hi, mid, lo;
-        split3(x[d], hi, mid, lo);
-        out[d] = hi;
-        out[D + d] = mid;
-        out[2 * D + d] = lo;
-        out[3 * D + d] = hi;
-        out[4 * D + d] = mid;
-        out[5 * D + d] = hi;
-      }
-      out[6 * D] = qh;
-      out[6 * D + 1] = qm;
-      out[6 * D + 2] = ql;
-      out[6 * D + 3] = qh;
-      out[6 * D + 4] = qm;
-      out[6 * D + 5] = qh;
+      parts[1] = cv(r);
     }
+  };
+  uint16_t qp[3];
+  split(q, qp);
+  if (shared_chunks(D, bf)) {
+    const int L = split_levels(bf);
+    for (int d = 0; d < D; ++d) {
+      uint16_t xp[3];
+      split(x[d], xp);
+      out[d] = xp[0];
+      if (bf) {
+        out[D + 4 + d] = xp[1];
+        out[2 * D + 4 + d] = xp[2];
+      } else {
+        out[D + 3 + d] = xp[1];
+      }
+    }
+    for (int l = 0; l <= L; ++l) out[D + l] = qp[l];
+  } else if (bf) {
+    for (int d = 0; d < D; ++d) {
+      uint16_t xp[3];
+      split(x[d], xp);
+      out[d] = xp[0];
+      out[D + d] = xp[1];
+      out[2 * D + d] = xp[2];
+      out[3 * D + d] = xp[0];
+      out[4 * D + d] = xp[1];
+      out[5 * D + d] = xp[0];
+    }
+    out[6 * D] = qp[0];
+    out[6 * D + 1] = qp[1];
+    out[6 * D + 2] = qp[2];
+    out[6 * D + 3] = qp[0];
+    out[6 * D + 4] = qp[1];
+    out[6 * D + 5] = qp[0];
+  } else {
+    for (int d = 0; d < D; ++d) {
+      uint16_t xp[3];
+      split(x[d], xp);
+      out[d] = xp[0];
+      out[D + d] = xp[1];
+      out[2 * D + d] = xp[0];
+    }
+    out[3 * D] = qp[0];
+    out[3 * D + 1] = qp[1];
+    out[3 * D + 2] = qp[0];
   }
   out[shift_slot(D, bf)] = cv(1.0);
 }

@@ -63,46 +63,59 @@ typedef float float16_t __attribute__((ext_vector_type(16)));
 
 constexpr int kTileLevels = kMaxBits - 5;   // label bits carried by the point-tile index
 
-// K slots of a point record, padded to whole 16-slot chunks (q = |x|^2):
-//  half precision: [x_hi | x_lo | x_hi | q_hi, q_lo, q_hi | 1], one product
-//    per chunk, the sample side pairing slot for slot;
-//  bfloat16, D <= 4: [x_hi | x_mid | x_lo | x_hi | x_mid | x_hi |
-//    q_hi, q_mid, q_lo, q_hi, q_mid, q_hi | 1], likewise one product per
-//    chunk;
-//  bfloat16, D > 4 (shared chunks): [x_hi | q_hi, q_mid, q_lo | 1 | x_mid |
-//    x_lo], each chunk taken by up to three products, one per split level of
-//    the sample side (hi, mid, lo), which pairs that level with the chunk's
-//    point parts whose levels leave a sum of at most 2.
-// Either bfloat16 form keeps the six products hi·hi, hi·mid, mid·hi, hi·lo,
-// lo·hi, mid·mid (the shift's 1 pairs with the hi level only). Sharing chunks
-// makes the records as small as the half-precision ones, which matters where
-// the run-time-M kernels stream them from L2; at D <= 4 the records fit one
-// or two chunks either way and the extra product per chunk costs more.
-__host__ __device__ constexpr bool bf_shared(int D) { return D > 4; }
+// K slots of a point record, padded to whole 16-slot chunks (q = |x|^2).
+// Slot for slot (one product per chunk, the sample side pairing each slot):
+//  half precision: [x_hi | x_lo | x_hi | q_hi, q_lo, q_hi | 1];
+//  bfloat16: [x_hi | x_mid | x_lo | x_hi | x_mid | x_hi |
+//    q_hi, q_mid, q_lo, q_hi, q_mid, q_hi | 1].
+// Shared chunks (each point part once):
+//  half precision: [x_hi | q_hi, q_lo | 1 | x_lo];
+//  bfloat16: [x_hi | q_hi, q_mid, q_lo | 1 | x_mid | x_lo];
+//  each chunk is taken by up to L + 1 products (L = 1 half, 2 bfloat16), one
+//  per split level l of the sample side, which pairs l with the chunk's point
+//  parts of level p <= L - l.
+// Both keep the same cross products (half: hi·hi, hi·lo, lo·hi; bfloat16:
+// hi·hi, hi·mid, mid·hi, hi·lo, lo·hi, mid·mid; the shift's 1 pairs with the
+// hi level only). Sharing makes the records smaller, which matters where the
+// run-time-M kernels stream them from L2; it is used where it saves a chunk
+// without costing a product (half precision, 10 <= D <= 15) or saves several
+// (bfloat16, D > 4: at D <= 4 the extra product per chunk costs more than
+// the smaller records save).
+__host__ __device__ constexpr bool shared_chunks(int D, bool bf) { return bf ? D > 4 : D >= 10 && D <= 15; }
+__host__ __device__ constexpr int split_levels(bool bf) { return bf ? 2 : 1; }   // L
+__host__ __device__ constexpr int record_slots(int D, bool bf) {
+  return shared_chunks(D, bf) ? (bf ? 3 * D + 4 : 2 * D + 3) : (bf ? 6 * D + 7 : 3 * D + 4);
+}
 __host__ __device__ constexpr int shift_slot(int D, bool bf) {
-  return !bf ? 3 * D + 3 : bf_shared(D) ? D + 3 : 6 * D + 6;
+  return shared_chunks(D, bf) ? D + split_levels(bf) + 1 : record_slots(D, bf) - 1;
 }
-__host__ __device__ constexpr int mfma_nk(int D, bool bf = false) {
-  return (bf && !bf_shared(D) ? 6 * D + 7 + 15 : 3 * D + 4 + 15) / 16;
+__host__ __device__ constexpr int mfma_nk(int D, bool bf = false) { return (record_slots(D, bf) + 15) / 16; }
+
+// Split level of the point part in slot s of a shared-chunk record (0 hi,
+// then mid, lo; the shift's 1 counts as the lowest level L), L + 1 for
+// padding (pairs with nothing).
+__host__ __device__ constexpr int shared_slot_level(int D, bool bf, int s) {
+  const int L = split_levels(bf);
+  return s < D ? 0
+       : s < D + L + 1 ? s - D
+       : s == D + L + 1 ? L
+       : s < record_slots(D, bf) ? (bf && s < 2 * D + 4 ? 1 : L)
+       : L + 1;
 }
 
-// Split level of the point part in bfloat16 slot s: 0 hi, 1 mid, 2 lo (the
-// shift's 1 counts as lo), 3 for padding (pairs with nothing).
-__host__ __device__ constexpr int bf_slot_level(int D, int s) {
-  return s < D ? 0 : s < D + 3 ? s - D : s == D + 3 ? 2 : s < 2 * D + 4 ? 1 : s < 3 * D + 4 ? 2 : 3;
-}
-
-// Products of the K chain: one per chunk, except in the shared-chunk
-// bfloat16 form, where a chunk takes as many as the sample levels its highest
-// point part pairs with (chunk by chunk, levels in increasing order).
+// Products of the K chain: one per chunk, except with shared chunks, where a
+// chunk takes as many as the sample levels its highest point part pairs with
+// (chunk by chunk, levels in increasing order).
 template <int D, bool BF>
 struct KPlan {
   static constexpr int NK = mfma_nk(D, BF);      // record chunks
+  static constexpr int L = split_levels(BF);
   static constexpr int levels(int c) {
-    if (!BF || !bf_shared(D)) return 1;
-    int lo = 3;
-    for (int s = 16 * c; s < 16 * c + 16; ++s) lo = bf_slot_level(D, s) < lo ? bf_slot_level(D, s) : lo;
-    return 3 - lo;
+    if (!shared_chunks(D, BF)) return 1;
+    int lo = L + 1;
+    for (int s = 16 * c; s < 16 * c + 16; ++s)
+      lo = shared_slot_level(D, BF, s) < lo ? shared_slot_level(D, BF, s) : lo;
+    return L + 1 - lo;
   }
   static constexpr int count() {
     int n = 0;
@@ -125,6 +138,10 @@ struct KPlan {
     return 0;
   }
 };
+static_assert(KPlan<12, false>::NK == 2 && KPlan<12, false>::NP == 3, "half-precision 12-D plan");
+static_assert(KPlan<8, true>::NK == 2 && KPlan<8, true>::NP == 5, "bfloat16 8-D plan");
+static_assert(KPlan<4, true>::NK == 2 && KPlan<4, true>::NP == 2, "bfloat16 4-D plan");
+static_assert(KPlan<8, false>::NK == 2 && KPlan<8, false>::NP == 2, "half-precision 8-D plan");
 
 template <bool BF> struct MfmaOp;
 template <> struct MfmaOp<false> {
@@ -180,6 +197,7 @@ __device__ __forceinline__ bool sample_operands(const float (&w)[D], float nc, f
                                                 typename MfmaOp<BF>::vec (&B)[KPlan<D, BF>::NP]) {
   typedef typename MfmaOp<BF>::elem E;
   typedef KPlan<D, BF> P;
+  constexpr int L = P::L;
   const uint32_t hmask = 0u - (uint32_t)h;
   auto pack = [hmask](E a0, E a1, E b0, E b1) {
     E p0[2] = {a0, a1}, p1[2] = {b0, b1};
@@ -188,47 +206,12 @@ __device__ __forceinline__ bool sample_operands(const float (&w)[D], float nc, f
     __builtin_memcpy(&w1, p1, 4);
     return (w0 & ~hmask) | (w1 & hmask);
   };
-  if constexpr (BF && !bf_shared(D)) {
-    E F[16 * P::NK];
-#pragma unroll
-    for (int k = 0; k < 16 * P::NK; ++k) F[k] = (E)0.0f;
-#pragma unroll
-    for (int d = 0; d < D; d += 2) {
-      const int d1 = d + 1 < D ? d + 1 : d;
-      __bf16 hi[2], mid[2], lo[2];
-      split3_bf16(w[d], d + 1 < D ? w[d1] : 0.0f, hi, mid, lo);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-        if (d + i < D) {
-          F[d + i] = hi[i];
-          F[D + d + i] = hi[i];
-          F[2 * D + d + i] = hi[i];
-          F[3 * D + d + i] = mid[i];
-          F[4 * D + d + i] = mid[i];
-          F[5 * D + d + i] = lo[i];
-        }
-    }
-    __bf16 hi[2], mid[2], lo[2];
-    split3_bf16(nc, 0.0f, hi, mid, lo);
-    F[6 * D] = hi[0];
-    F[6 * D + 1] = hi[0];
-    F[6 * D + 2] = hi[0];
-    F[6 * D + 3] = mid[0];
-    F[6 * D + 4] = mid[0];
-    F[6 * D + 5] = lo[0];
-    F[shift_slot(D, true)] = (E)S;
-#pragma unroll
-    for (int kk = 0; kk < P::NK; ++kk) {
-      uint32_t wd[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        wd[q] = pack(F[16 * kk + 2 * q], F[16 * kk + 2 * q + 1], F[16 * kk + 8 + 2 * q], F[16 * kk + 9 + 2 * q]);
-      __builtin_memcpy(&B[kk], wd, 16);
-    }
-    return true;
-  } else if constexpr (BF) {
-    // shared chunks: hi, mid, lo of every w_d and of nc
-    E wl[3][D], nl[3];
+  // the split parts of every w_d and of nc: wl[level][d], nl[level]
+  // (half precision: hi, lo, two dimensions at a time with the packed RNE
+  // conversion; bfloat16: hi, mid, lo)
+  E wl[L + 1][D], nl[L + 1];
+  bool ok = true;
+  if constexpr (BF) {
 #pragma unroll
     for (int d = 0; d < D; d += 2) {
       const int d1 = d + 1 < D ? d + 1 : d;
@@ -239,25 +222,45 @@ __device__ __forceinline__ bool sample_operands(const float (&w)[D], float nc, f
         if (d + i < D) {
           wl[0][d + i] = hi[i];
           wl[1][d + i] = mid[i];
-          wl[2][d + i] = lo[i];
+          wl[L][d + i] = lo[i];
         }
     }
-    {
-      __bf16 hi[2], mid[2], lo[2];
-      split3_bf16(nc, 0.0f, hi, mid, lo);
-      nl[0] = hi[0];
-      nl[1] = mid[0];
-      nl[2] = lo[0];
+    __bf16 hi[2], mid[2], lo[2];
+    split3_bf16(nc, 0.0f, hi, mid, lo);
+    nl[0] = hi[0];
+    nl[1] = mid[0];
+    nl[L] = lo[0];
+  } else {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    ok = __builtin_fabsf(nc) < 60000.0f;
+#pragma unroll
+    for (int d = 0; d < D; d += 2) {
+      const float w0 = w[d];
+      const float w1 = d + 1 < D ? w[d + 1 < D ? d + 1 : d] : 0.0f;
+      ok &= __builtin_fmaxf(__builtin_fabsf(w0), __builtin_fabsf(w1)) < 60000.0f;
+      const f2 wv = {w0, w1};
+      const h2 hi = __builtin_convertvector(wv, h2);
+      const h2 lo = __builtin_convertvector(wv - __builtin_convertvector(hi, f2), h2);
+      wl[0][d] = hi.x;
+      wl[L][d] = lo.x;
+      if (d + 1 < D) {
+        wl[0][d + 1] = hi.y;
+        wl[L][d + 1] = lo.y;
+      }
     }
-    const E sb = (E)S;
+    split2(nc, nl[0], nl[L]);
+  }
+  const E sb = (E)S;
+  if constexpr (shared_chunks(D, BF)) {
     // the sample value that slot s pairs with at level l (0 if none)
     auto val = [&](int s, int l) -> E {
-      if (bf_slot_level(D, s) + l > 2) return (E)0.0f;
+      if (shared_slot_level(D, BF, s) + l > L) return (E)0.0f;
       if (s < D) return wl[l][s];
-      if (s < D + 3) return nl[l];
-      if (s == D + 3) return sb;
-      if (s < 2 * D + 4) return wl[l][s - D - 4];
-      return wl[l][s - 2 * D - 4];
+      if (s < D + L + 1) return nl[l];
+      if (s == D + L + 1) return sb;
+      if (BF && s < 2 * D + 4) return wl[l][s - D - 4];
+      return wl[l][s - (BF ? 2 * D + 4 : D + 3)];
     };
 #pragma unroll
     for (int p = 0; p < P::NP; ++p) {
@@ -268,39 +271,40 @@ __device__ __forceinline__ bool sample_operands(const float (&w)[D], float nc, f
         wd[q] = pack(val(c0 + 2 * q, l), val(c0 + 2 * q + 1, l), val(c0 + 8 + 2 * q, l), val(c0 + 9 + 2 * q, l));
       __builtin_memcpy(&B[p], wd, 16);
     }
-    return true;
   } else {
-    // half precision: two dimensions at a time with the packed conversion
-    // (round to nearest even), which writes whole registers
-    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-    typedef float f2 __attribute__((ext_vector_type(2)));
+    // slot for slot: the features in record order, then each lane's half of
+    // every chunk
     E F[16 * P::NK];
 #pragma unroll
     for (int k = 0; k < 16 * P::NK; ++k) F[k] = (E)0.0f;
-    bool ok = __builtin_fabsf(nc) < 60000.0f;
 #pragma unroll
-    for (int d = 0; d < D; d += 2) {
-      const float w0 = w[d];
-      const float w1 = d + 1 < D ? w[d + 1 < D ? d + 1 : d] : 0.0f;
-      ok &= __builtin_fmaxf(__builtin_fabsf(w0), __builtin_fabsf(w1)) < 60000.0f;
-      const f2 wv = {w0, w1};
-      const h2 hi = __builtin_convertvector(wv, h2);
-      const h2 lo = __builtin_convertvector(wv - __builtin_convertvector(hi, f2), h2);
-      F[d] = hi.x;
-      F[D + d] = hi.x;
-      F[2 * D + d] = lo.x;
-      if (d + 1 < D) {
-        F[d + 1] = hi.y;
-        F[D + d + 1] = hi.y;
-        F[2 * D + d + 1] = lo.y;
+    for (int d = 0; d < D; ++d) {
+      if constexpr (BF) {
+        F[d] = wl[0][d];
+        F[D + d] = wl[0][d];
+        F[2 * D + d] = wl[0][d];
+        F[3 * D + d] = wl[1][d];
+        F[4 * D + d] = wl[1][d];
+        F[5 * D + d] = wl[2][d];
+      } else {
+        F[d] = wl[0][d];
+        F[D + d] = wl[0][d];
+        F[2 * D + d] = wl[1][d];
       }
     }
-    _Float16 hi, lo;
-    split2(nc, hi, lo);
-    F[3 * D] = hi;
-    F[3 * D + 1] = hi;
-    F[3 * D + 2] = lo;
-    F[shift_slot(D, false)] = (E)S;
+    if constexpr (BF) {
+      F[6 * D] = nl[0];
+      F[6 * D + 1] = nl[0];
+      F[6 * D + 2] = nl[0];
+      F[6 * D + 3] = nl[1];
+      F[6 * D + 4] = nl[1];
+      F[6 * D + 5] = nl[2];
+    } else {
+      F[3 * D] = nl[0];
+      F[3 * D + 1] = nl[0];
+      F[3 * D + 2] = nl[1];
+    }
+    F[shift_slot(D, BF)] = sb;
 #pragma unroll
     for (int kk = 0; kk < P::NK; ++kk) {
       uint32_t wd[4];
@@ -309,8 +313,8 @@ __device__ __forceinline__ bool sample_operands(const float (&w)[D], float nc, f
         wd[q] = pack(F[16 * kk + 2 * q], F[16 * kk + 2 * q + 1], F[16 * kk + 8 + 2 * q], F[16 * kk + 9 + 2 * q]);
       __builtin_memcpy(&B[kk], wd, 16);
     }
-    return ok;
   }
+  return ok;
 }
 
 // The two values a lane pair (l, l + 32) holds: lo from lane l, hi from lane
