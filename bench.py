@@ -37,11 +37,12 @@ FEC_OVERHEAD = [0.067, 0.20]
 FEC_THRESHOLD = [3.8e-3, 2.0e-2]
 
 
-# Sources of the matrix-core first tier and of its launch (grid, arguments):
-# stored counter data describes the kernel only while these are unchanged.
+# Sources of the profiled kernels (both tiers) and of their launches (grid,
+# arguments): stored counter data describes the kernels only while these are
+# unchanged.
 FIRST_TIER_SOURCES = ("device_common.h", "mfma_kernels.h", "mfma_wide.h", "mfma_inst_f16_0.hip",
                       "mfma_inst_bf16_0.hip", "vec_kernels.h", "vec_inst_f32_0.hip", "air_host.hip",
-                      "host_state.h")
+                      "host_state.h", "tier2_list.h", "exact_rule.h")
 
 
 def source_hash() -> str:
