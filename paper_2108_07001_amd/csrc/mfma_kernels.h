@@ -186,25 +186,22 @@ __device__ __forceinline__ void split3_bf16(float v0, float v1, __bf16 (&hi)[2],
   lo[1] = l.y;
 }
 
-// Sample-side operands of this lane's K half (h) for the products of the K
+// Sample-side operand words of both K halves for the products of the K
 // chain, from w = 2 c y, nc = -c and the value S of the shift slot (0 when
-// the accumulator carries the shift), in the order of the point records.
-// The halves are selected on packed 32-bit words so that the choice never
-// becomes an index. Returns false when a value leaves the half-precision
+// the accumulator carries the shift), in the order of the point records:
+// emit(p, q, word of half 0, word of half 1) for product p and packed word q
+// (0..3) of the half. Returns false when a value leaves the half-precision
 // range (bfloat16 has the FP32 range).
-template <int D, bool BF>
-__device__ __forceinline__ bool sample_operands(const float (&w)[D], float nc, float S, int h,
-                                                typename MfmaOp<BF>::vec (&B)[KPlan<D, BF>::NP]) {
+template <int D, bool BF, class Emit>
+__device__ __forceinline__ bool sample_words(const float (&w)[D], float nc, float S, Emit&& emit) {
   typedef typename MfmaOp<BF>::elem E;
   typedef KPlan<D, BF> P;
   constexpr int L = P::L;
-  const uint32_t hmask = 0u - (uint32_t)h;
-  auto pack = [hmask](E a0, E a1, E b0, E b1) {
-    E p0[2] = {a0, a1}, p1[2] = {b0, b1};
-    uint32_t w0, w1;
-    __builtin_memcpy(&w0, p0, 4);
-    __builtin_memcpy(&w1, p1, 4);
-    return (w0 & ~hmask) | (w1 & hmask);
+  auto word = [](E a0, E a1) {
+    E pr[2] = {a0, a1};
+    uint32_t v;
+    __builtin_memcpy(&v, pr, 4);
+    return v;
   };
   // the split parts of every w_d and of nc: wl[level][d], nl[level]
   // (half precision: hi, lo, two dimensions at a time with the packed RNE
@@ -265,11 +262,9 @@ __device__ __forceinline__ bool sample_operands(const float (&w)[D], float nc, f
 #pragma unroll
     for (int p = 0; p < P::NP; ++p) {
       const int c0 = 16 * P::chunk(p), l = P::level(p);
-      uint32_t wd[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        wd[q] = pack(val(c0 + 2 * q, l), val(c0 + 2 * q + 1, l), val(c0 + 8 + 2 * q, l), val(c0 + 9 + 2 * q, l));
-      __builtin_memcpy(&B[p], wd, 16);
+        emit(p, q, word(val(c0 + 2 * q, l), val(c0 + 2 * q + 1, l)), word(val(c0 + 8 + 2 * q, l), val(c0 + 9 + 2 * q, l)));
     }
   } else {
     // slot for slot: the features in record order, then each lane's half of
@@ -306,14 +301,26 @@ __device__ __forceinline__ bool sample_operands(const float (&w)[D], float nc, f
     }
     F[shift_slot(D, BF)] = sb;
 #pragma unroll
-    for (int kk = 0; kk < P::NK; ++kk) {
-      uint32_t wd[4];
+    for (int kk = 0; kk < P::NK; ++kk)
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        wd[q] = pack(F[16 * kk + 2 * q], F[16 * kk + 2 * q + 1], F[16 * kk + 8 + 2 * q], F[16 * kk + 9 + 2 * q]);
-      __builtin_memcpy(&B[kk], wd, 16);
-    }
+        emit(kk, q, word(F[16 * kk + 2 * q], F[16 * kk + 2 * q + 1]), word(F[16 * kk + 8 + 2 * q], F[16 * kk + 9 + 2 * q]));
   }
+  return ok;
+}
+
+// Sample-side operands of this lane's K half (h), selected on packed 32-bit
+// words so that the choice never becomes an index.
+template <int D, bool BF>
+__device__ __forceinline__ bool sample_operands(const float (&w)[D], float nc, float S, int h,
+                                                typename MfmaOp<BF>::vec (&B)[KPlan<D, BF>::NP]) {
+  const uint32_t hmask = 0u - (uint32_t)h;
+  uint32_t wd[KPlan<D, BF>::NP][4];
+  const bool ok = sample_words<D, BF>(w, nc, S, [&](int p, int q, uint32_t w0, uint32_t w1) {
+    wd[p][q] = (w0 & ~hmask) | (w1 & hmask);
+  });
+#pragma unroll
+  for (int p = 0; p < KPlan<D, BF>::NP; ++p) __builtin_memcpy(&B[p], wd[p], 16);
   return ok;
 }
 

@@ -199,6 +199,48 @@ struct WideOperand {
     ovf = BF ? false : !(yy < yy_lim);
   }
 
+  // Operands of both 32-sample groups from this lane's own sample (group h of
+  // the lane's column: group A's samples live in lanes 0..31, group B's in
+  // 32..63). The lane forms both K halves of its own sample's operand; one
+  // v_permlane32_swap per word then hands every lane its K half of both
+  // groups' operands, so no lane forms another lane's sample. ovf is the own
+  // sample's.
+  static __device__ __forceinline__ void build_pair(const float (&y)[D], float c, float yy_lim, int m,
+                                                    WideOperand& opA, WideOperand& opB) {
+    const float K = Real<float>::shift(m);
+    float yy = 0.0f;
+#pragma unroll
+    for (int d = 0; d < D; ++d) yy = __builtin_fmaf(y[d], y[d], yy);
+    float w[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) w[d] = 2.0f * c * y[d];
+    const float s0 = __builtin_fmaf(-c, yy, K);
+    const float ulp = BF ? 0x1p-7f : 0x1p-10f;
+    uint32_t w0[NP][4], w1[NP][4];
+    (void)sample_words<D, BF>(w, -c, s0 - __builtin_fabsf(s0) * ulp,
+                              [&](int p, int q, uint32_t a, uint32_t b) {
+                                w0[p][q] = a;
+                                w1[p][q] = b;
+                              });
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      uint32_t wa[4], wb[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        // lanes 0..31 keep their half 0 and take half 0 of lane + 32 (group
+        // B); lanes 32..63 keep their half 1 and take half 1 of lane - 32
+        const auto r = __builtin_amdgcn_permlane32_swap(w0[p][q], w1[p][q], false, false);
+        wa[q] = r[0];
+        wb[q] = r[1];
+      }
+      __builtin_memcpy(&opA.B[p], wa, 16);
+      __builtin_memcpy(&opB.B[p], wb, 16);
+    }
+    const bool o = BF ? false : !(yy < yy_lim);
+    opA.ovf = o;
+    opB.ovf = o;
+  }
+
   __device__ __forceinline__ float16_t product(const V (&A)[NK]) const {
     const float16_t zero = {};
     float16_t acc = MfmaOp<BF>::mma(A[KPlan<D, BF>::chunk(0)], B[0], zero);
@@ -363,6 +405,10 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
   constexpr int NE = HALF ? 8 : 16;
   constexpr int NEB = HALF ? 3 : 4;       // element bits carrying label bits
   constexpr bool MARG = MB == 5 || MB == 6;  // one or two point tiles: TileMarg
+  // each lane forms only its own sample's operand (build_pair): fewer
+  // instructions per round, which the small sets feel; the run-time-M forms
+  // of D > 8 measured 2 % slower with it (12-D/4096) and keep the per-group form
+  constexpr bool OWN = MB != 0 || D <= 8;
   extern __shared__ double acc_lds[];      // [waves][S][4], then the tables (TBL)
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
@@ -416,36 +462,60 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
     // WideOperand::build); none at all if c itself is out of range
     const float yy_lim = sp.c < 60000.0f ? __builtin_fminf(59000.0f, 9.0e8f / sp.c) / sp.c : -1.0f;
     const int64_t q0 = (wgid + ((((int64_t)s * rem) % wstride) & ~(int64_t)31)) % wstride;
+    // OWN: each lane sets up its own sample only (group A, tile 2 q, in
+    // lanes 0..31; group B, tile 2 q + 1, in lanes 32..63) and forms both K
+    // halves of its operand (build_pair); otherwise every lane sets up both
+    // groups' samples of its column and forms its K half of each
     RawInput<D> inA, inB;
     if (q0 < npairs) {
-      inA.fetch(sp, 2 * q0, j);
-      inB.fetch(sp, 2 * q0 + 1, j);
+      if constexpr (OWN) {
+        inA.fetch(sp, 2 * q0 + h, j);
+      } else {
+        inA.fetch(sp, 2 * q0, j);
+        inB.fetch(sp, 2 * q0 + 1, j);
+      }
     }
     for (int64_t q = q0; q < npairs; q += wstride) {
       WideSample<D> smA, smB;
-      smA.setup(sp, tb, 2 * q, j, s == 0 && h == 0, inA);
-      smB.setup(sp, tb, 2 * q + 1, j, s == 0 && h == 0, inB);
-      {
+      const int64_t qn = q + wstride < npairs ? q + wstride : npairs - 1;
+      OP opA, opB;
+      if constexpr (OWN) {
+        smA.setup(sp, tb, 2 * q + h, j, s == 0, inA);
         // the next round's inputs, loaded into the registers just consumed
         // (no copy between buffers) a round ahead of use
-        const int64_t qn = q + wstride < npairs ? q + wstride : npairs - 1;
+        inA.fetch(sp, 2 * qn + h, j);
+        OP::build_pair(smA.y, sp.c, yy_lim, m, opA, opB);
+      } else {
+        smA.setup(sp, tb, 2 * q, j, s == 0 && h == 0, inA);
+        smB.setup(sp, tb, 2 * q + 1, j, s == 0 && h == 0, inB);
         inA.fetch(sp, 2 * qn, j);
         inB.fetch(sp, 2 * qn + 1, j);
+        opA.build(smA.y, sp.c, yy_lim, m, h);
+        opB.build(smB.y, sp.c, yy_lim, m, h);
       }
-      OP opA, opB;
-      opA.build(smA.y, sp.c, yy_lim, m, h);
-      opB.build(smB.y, sp.c, yy_lim, m, h);
+      // the lane's own sample
+      const WideSample<D>& sm = (OWN || !h) ? smA : smB;
 
       // the transmitted points' own terms: diagonals of the products whose A
-      // rows are the groups' transmitted points
+      // rows are the groups' transmitted points (OWN: both groups' labels of
+      // this column in every lane by one exchange between the lane halves)
       float arg_t = 0.f;
       if (!ML && a.tx) {
+        int tqA, tqB;
+        if constexpr (OWN) {
+          const auto tqs = __builtin_amdgcn_permlane32_swap((uint32_t)smA.tq, (uint32_t)smA.tq, false, false);
+          tqA = (int)tqs[0];
+          tqB = (int)tqs[1];
+        } else {
+          tqA = smA.tq;
+          tqB = smB.tq;
+        }
         V At[NK];
-        const V* ra = tb.rec + ((int64_t)smA.tq * NK) * 2 + h;
+        const V* ra = tb.rec + ((int64_t)tqA * NK) * 2 + h;
 #pragma unroll
         for (int kk = 0; kk < NK; ++kk) At[kk] = ra[2 * kk];
         const float pa = diag_pick(opA.product(At), j);
-        const V* rb = tb.rec + ((int64_t)smB.tq * NK) * 2 + h;
+        const V* rb = tb.rec + ((int64_t)tqB * NK) * 2 + h;
 #pragma unroll
         for (int kk = 0; kk < NK; ++kk) At[kk] = rb[2 * kk];
         const float pb = diag_pick(opB.product(At), j);
@@ -485,11 +555,11 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
         }
       }
       // own sample of this lane: group A in lanes 0..31, group B in 32..63
-      const int64_t n = h ? smB.n : smA.n;
-      const bool valid = h ? smB.valid : smA.valid;
-      const bool live = h ? smB.live : smA.live;
-      const int tl = h ? smB.tl : smA.tl;
-      const bool ovf = h ? opB.ovf : opA.ovf;
+      const int64_t n = sm.n;
+      const bool valid = sm.valid;
+      const bool live = sm.live;
+      const int tl = sm.tl;
+      const bool ovf = (OWN || !h) ? opA.ovf : opB.ovf;
 
       float side[2 * kMaxBits];
 #pragma unroll
@@ -581,10 +651,7 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
         (void)total;
         (void)thr;
         if (live && ovf) {
-          float yo[D];
-#pragma unroll
-          for (int d = 0; d < D; ++d) yo[d] = h ? smB.y[d] : smA.y[d];
-          maxlog_direct<D>(yo, tb.xl, a.M, m, sp.c, side);
+          maxlog_direct<D>(sm.y, tb.xl, a.M, m, sp.c, side);
           ++nlisted;                       // counted as recomputed below
         }
         float v = 0.f;
