@@ -406,9 +406,11 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
   constexpr int NEB = HALF ? 3 : 4;       // element bits carrying label bits
   constexpr bool MARG = MB == 5 || MB == 6;  // one or two point tiles: TileMarg
   // each lane forms only its own sample's operand (build_pair): fewer
-  // instructions per round, which the small sets feel; the run-time-M forms
-  // of D > 8 measured 2 % slower with it (12-D/4096) and keep the per-group form
-  constexpr bool OWN = MB != 0 || D <= 8;
+  // instructions per round, which the small sets feel; the half-precision
+  // run-time-M forms of D > 8 measured 2 % slower with it (12-D/4096) and keep
+  // the per-group form (in bfloat16 it is 1 % faster there and ends the
+  // spills of the 12-D form)
+  constexpr bool OWN = MB != 0 || D <= 8 || BF;
   extern __shared__ double acc_lds[];      // [waves][S][4], then the tables (TBL)
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
