@@ -336,6 +336,18 @@ __device__ __forceinline__ bool finish_item(const ExactArgs<T>& a, int64_t n, in
   return slow;
 }
 
+// floor(x) as an integer in one instruction (v_cvt_flr_i32_f32; the compiler
+// forms it from a floor and a conversion). For finite x within the int range.
+// `after` is a value the compiler formed from x (the fraction of x): the
+// instruction is held behind it, so when x is a matrix-core result the
+// compiler's own wait states before that reader cover this one too (it does
+// not place them before inline assembly).
+__device__ __forceinline__ int floor_i32(float x, float after) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x), "v"(after));
+  return r;
+}
+
 // log2 of a positive double through its binary exponent and an FP32 log2 of
 // the mantissa: absolute error ~2e-7, far inside every tolerance on the
 // quantities it feeds (differences of such logs), at a fraction of the cost

@@ -694,7 +694,7 @@ __device__ __forceinline__ bool tier2_tile(const SampleTile<D, BF>& smp, const T
   const int dK = K64 - (int)Real<float>::shift(m);
   auto val64 = [&](float x) -> double {
     const float fr = __builtin_amdgcn_fractf(x);    // x - floor(x), in [0, 1)
-    const int ni = (int)__builtin_floorf(x);
+    const int ni = floor_i32(x, fr);
     return __builtin_ldexp((double)Real<float>::exp2(fr), ni + dK);
   };
   TileSums<double, NE> ts;

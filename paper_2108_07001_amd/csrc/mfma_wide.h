@@ -333,6 +333,14 @@ struct WideSample {
   }
 };
 
+// Flagged samples in one 64-sample round from which a wave of the run-time-M
+// first tier hands the rest of its rounds at that SNR point to the second
+// tier directly: above a flagged fraction of about 0.55 (12-D, M = 4096) to
+// 0.74 (8-D, M = 2048) that is the cheaper route, since the second tier
+// costs about 2.5 times the first tier per term and re-forms every flagged
+// sample anyway.
+constexpr int kDirectRound = 48;
+
 // First tier, 64 samples per wave round. The exact-size forms of small D are
 // held to 168 registers (three waves per SIMD); what little the allocator
 // then keeps in scratch is reloaded once per SNR point, outside the sample
@@ -411,6 +419,12 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
   // the per-group form (in bfloat16 it is 1 % faster there and ends the
   // spills of the 12-D form)
   constexpr bool OWN = MB != 0 || D <= 8 || BF;
+  // run-time-M forms: once a round of a wave has had at least kDirectRound of
+  // its 64 samples flagged for the second tier, the wave's later rounds at
+  // that SNR point list every live sample for the second tier without
+  // forming them here (at high SNR nearly every sample of a large set has a
+  // bit side below the FP32 frame, and the first tier's work on it is lost)
+  constexpr bool DIRECT = MB == 0 && !ML;
   extern __shared__ double acc_lds[];      // [waves][S][4], then the tables (TBL)
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
@@ -477,7 +491,8 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
         inB.fetch(sp, 2 * q0 + 1, j);
       }
     }
-    for (int64_t q = q0; q < npairs; q += wstride) {
+    int64_t q = q0;
+    for (; q < npairs; q += wstride) {
       WideSample<D> smA, smB;
       const int64_t qn = q + wstride < npairs ? q + wstride : npairs - 1;
       OP opA, opB;
@@ -730,6 +745,36 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
         av += dv;
         auu = __builtin_fma(du, du, auu);
         avv = __builtin_fma(dv, dv, avv);
+      }
+      if constexpr (DIRECT) {
+        if (__builtin_popcountll(bm) >= kDirectRound) {
+          q += wstride;
+          break;
+        }
+      }
+    }
+    if constexpr (DIRECT) {
+      // the rest of the wave's rounds at this SNR point: every live sample
+      // (the lane's own one, sample tile 2 q + h) listed as it is
+      for (; q < npairs; q += wstride) {
+        const int64_t n = (2 * q + h) * 32 + j;
+        const bool valid = n < sp.N;
+        const uint32_t t = (valid && sp.tx) ? sp.tx[n] : 0u;
+        const bool bad = valid && sp.tx && !(t < (uint32_t)sp.M);
+        if (s == 0 && bad) atomicOr(sp.err, 1);
+        if (bad && llr)
+          for (int k = 0; k < m; ++k) llr[(int64_t)s * a.llr_stride_s + n * m + k] = Real<float>::nan();
+        const unsigned long long bm = __ballot(valid && !bad);
+        const unsigned long long mlo = bm & 0xffffffffull, mhi = bm >> 32;
+        nflag += __builtin_popcountll(bm);
+        if (mlo) {
+          if (lane == 0) slots[nlisted] = (mlo << 32) | (unsigned long long)(2 * q);
+          ++nlisted;
+        }
+        if (mhi) {
+          if (lane == 0) slots[nlisted] = (mhi << 32) | (unsigned long long)(2 * q + 1);
+          ++nlisted;
+        }
       }
     }
     if constexpr (ML) {

@@ -11,9 +11,14 @@ workload within a test, so
 (b) the LLRs of a random sample of received points are checked one by one
     against the oracle run on exactly those points;
 (c) the full-size MI/GMI must equal the sample-weighted combination of two
-    calls on the halves of the block (the sums are additive, so this holds at
-    any size up to FP64 rounding; it catches lost or doubled tiles, lists and
-    partial sums)."""
+    calls on the halves of the block (the sums are additive; it catches lost
+    or doubled tiles, lists and partial sums). A sample's products are the
+    same in both calls, but which tier finishes it can differ: a wave of the
+    large sets' first tier hands its later rounds at an SNR point to the
+    second tier once a round has mostly been flagged, and the rounds a wave
+    sees depend on the block size. The two tiers agree to FP32 rounding
+    (~1e-7 bit per sample), so the combination is held to 1e-7 bit; a lost
+    or doubled tile of 32 samples moves the mean by ~1e-5."""
 import json
 import os
 
@@ -83,7 +88,7 @@ def _halves_consistent(ctx, c, w, st_full, prec):
                           w.snr_db, prec=prec)
         parts.append((hi - lo, st.cpu().numpy()))
     comb = sum(n * s[:, :2] for n, s in parts) / N
-    np.testing.assert_allclose(st_full[:, :2], comb, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(st_full[:, :2], comb, rtol=0, atol=1e-7)
 
 
 @pytest.mark.parametrize("prec", ["fp16x3", "bf16x3"])
