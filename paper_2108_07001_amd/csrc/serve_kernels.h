@@ -66,6 +66,11 @@ __device__ __forceinline__ SampleParams job_params(const JobDesc& jd) {
   return SampleParams{jd.in, jd.tx, jd.N, jd.M, jd.m, jd.sweep, jd.c, jd.sigma, &jd.out->err};
 }
 
+// Flagged samples of a 32-sample tile from which a serving work item hands
+// its remaining tiles to the second tier directly (three quarters, as in the
+// sweep's first tier).
+constexpr int kDirectTile = 24;
+
 template <int D, bool BF, bool HALF>
 __global__ __launch_bounds__(256) void serve_tier1(const JobDesc* __restrict__ jobs, int njobs,
                                                    int64_t nitems) {
@@ -91,16 +96,28 @@ __global__ __launch_bounds__(256) void serve_tier1(const JobDesc* __restrict__ j
     unsigned long long* slots = jd.list + li * jd.chunk;
     double au = 0.0, av = 0.0, auu = 0.0, avv = 0.0;
     int nlisted = 0;
+    // once a tile of the item has had at least kDirectTile of its 32 samples
+    // flagged, the item's later tiles go to the second tier as they are (as
+    // in the sweep's first tier; the item's tiles are a function of the job
+    // alone, so the choice is too)
+    bool direct = false;
     for (int64_t st = st0; st < st1; ++st) {
       TileInput<D> ti;
       ti.load(sp, tb, st, j);
       ST smp;
       smp.setup(sp, st, j, h, true, ti);
       float* lout = (jd.llr && smp.valid) ? jd.llr + smp.n * m : nullptr;
-      float u, v;
+      float u = 0.f, v = 0.f;
       bool need2;
-      tier1_tile<D, BF, HALF>(smp, tb, jd.tx != nullptr, j, h, m, NT, ntb, thr, lout, u, v, need2);
+      if (!direct) {
+        tier1_tile<D, BF, HALF>(smp, tb, jd.tx != nullptr, j, h, m, NT, ntb, thr, lout, u, v, need2);
+      } else {
+        need2 = smp.live;
+        if (smp.valid && !smp.live && lout && h == 0)
+          for (int k = 0; k < m; ++k) lout[k] = Real<float>::nan();
+      }
       const unsigned long long fm = __ballot(need2 && h == 0) & 0xffffffffull;
+      if (!HALF && __builtin_popcountll(fm) >= kDirectTile) direct = true;
       if (fm != 0) {
         if (lane == 0) slots[nlisted] = (fm << 32) | (unsigned long long)st;
         ++nlisted;
