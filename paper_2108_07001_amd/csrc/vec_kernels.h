@@ -317,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void demap_vec_t2(const DemapArgs a, const 
   // an integer, so the fraction and the floor of x serve for those of a_j
   auto val64 = [&](float x) -> double {
     const float fr = __builtin_amdgcn_fractf(x);    // x - floor(x), in [0, 1)
-    const int ni = floor_i32(x, fr);
+    const int ni = (int)__builtin_floorf(x);
     return __builtin_ldexp((double)Real<float>::exp2(fr), ni + dK);
   };
   float* __restrict__ llr = static_cast<float*>(a.llr);

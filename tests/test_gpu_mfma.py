@@ -151,6 +151,38 @@ def test_invalid_tx(ctx):
     assert np.isnan(Lh[0, 999]).all() and np.isfinite(Lh[0, :999]).all()
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_direct_rounds_at_high_snr(ctx, prec):
+    # 8-D, M = 2048 at 24 dB: ~98 % of the samples have a bit side below the
+    # first tier's FP32 frame, so after one mostly flagged round every wave
+    # lists its later rounds for the second tier as they are. N = 1e6 gives
+    # each of the 6144 waves two or three rounds. Sampled LLRs (taken from
+    # all over the block, most from those later rounds) against the oracle,
+    # and a bad transmitted index in a late round: NaN LLRs for that sample
+    # only, and the range error.
+    w = inputs.make("gauss8d2048", N=1_000_000, snr_db=[24.0])
+    c = ctx.const(w.X, w.labels)
+    z = to_dev(w.z)
+    st, L = ctx.sweep(c, tx_dev(w.tx), z, w.snr_db, prec=prec, llr=True)
+    ctx.sync()
+    assert ctx.last_recomputed() >= 0.97 * w.N
+    idx = np.sort(np.random.default_rng(3).choice(w.N, size=120, replace=False))
+    got = L[:, torch.from_numpy(idx).to(L.device), :].cpu().numpy()
+    ref = oracle.sweep(w.X, w.labels, w.tx[idx], w.z[idx], w.snr_db)
+    assert_llr(got, ref["llr"], LLR_BAR[prec])
+    assert np.isfinite(st.cpu().numpy()).all()
+    tx = w.tx.astype(np.int32).copy()
+    bad = w.N - 1                          # the last pair: a wave's later round
+    tx[bad] = 1 << 20
+    st2, L2 = ctx.sweep(c, tx_dev(tx), z, w.snr_db, prec=prec, llr=True)
+    with pytest.raises(air.AirError) as e:
+        ctx.sync()
+    assert e.value.status == air.AIR_E_RANGE
+    Lh = L2[0, bad - 2:].cpu().numpy()
+    assert np.isnan(Lh[2]).all() and np.isfinite(Lh[:2]).all()
+    c.close()
+
+
 def test_call_words_start_clean(ctx):
     # the per-call words (tx-range error, second-tier counts) are zeroed by
     # the previous call's last kernel: counts and errors never carry over
