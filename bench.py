@@ -431,8 +431,11 @@ def large_sets(ctx, names, steps: int) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # 200 steps of ~0.35-0.7 ms: four interleaved segments of 50 per form, so
+    # that the launch latency at the start of a segment and the final
+    # synchronisation (~20 us each segment) stay well under 1 % of a step
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="psk8x8")
     ap.add_argument("--prec", default=None, help="fp32 | bf16x3 | fp16x3 (default: fastest)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
