@@ -25,7 +25,7 @@ __global__ __launch_bounds__(kBlock) void noise_var_kernel(const T* __restrict__
                                                            int* err) {
   __shared__ double wsum[kBlock / 64][kMaxD];
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
   double acc[kMaxD];
 #pragma unroll
   for (int d = 0; d < kMaxD; ++d) acc[d] = 0.0;

@@ -34,7 +34,7 @@ template <int D, int G>
 __global__ __launch_bounds__(kBlock) void hd_kernel(const HdArgs a) {
   __shared__ unsigned long long part[kBlock / 64][2];
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
   const int M = a.M;
   const int NG = M / G;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;

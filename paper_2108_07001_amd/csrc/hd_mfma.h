@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256, 2) void hd_mfma(const HdArgs a, const MfmaOp<f
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
   const int j = lane & 31;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
   const int waves = blockDim.x >> 6;
   const int M = a.M;
   const int NT = M >> 5;

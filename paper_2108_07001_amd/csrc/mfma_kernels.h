@@ -805,7 +805,7 @@ __global__ __launch_bounds__(256, D <= 12 ? 2 : 1) void demap_mfma_t2(const Dema
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
   const int j = lane & 31;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
   const int waves = blockDim.x >> 6;
   const int S = a.S;
   // the SNR runs in the tile sequence: lane s holds run s's padded start and its

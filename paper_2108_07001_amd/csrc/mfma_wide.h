@@ -429,7 +429,7 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
   const int j = lane & 31;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
   const int waves = blockDim.x >> 6;
   const int S = a.S;
   Tables<BF> tb{a.lab, xl, rec};

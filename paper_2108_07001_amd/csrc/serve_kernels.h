@@ -81,7 +81,8 @@ __global__ __launch_bounds__(256) void serve_tier1(const JobDesc* __restrict__ j
   const int j = lane & 31;
   const int64_t waves = blockDim.x >> 6;
   const int64_t wstride = (int64_t)gridDim.x * waves;
-  for (int64_t it = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6); it < nitems; it += wstride) {
+  for (int64_t it = (int64_t)blockIdx.x * waves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); it < nitems;
+       it += wstride) {
     const JobDesc& jd = jobs[serve_job_of(jobs, njobs, it)];
     const int64_t li = it - jd.item0;
     const int m = jd.m;
@@ -153,7 +154,8 @@ __global__ __launch_bounds__(256, D <= 12 ? 2 : 1) void serve_tier2(const JobDes
   const int j = lane & 31;
   const int64_t waves = blockDim.x >> 6;
   const int64_t wstride = (int64_t)gridDim.x * waves;
-  for (int64_t it = (int64_t)blockIdx.x * waves + (threadIdx.x >> 6); it < nitems; it += wstride) {
+  for (int64_t it = (int64_t)blockIdx.x * waves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); it < nitems;
+       it += wstride) {
     const JobDesc& jd = jobs[serve_job_of(jobs, njobs, it)];
     const int64_t li = it - jd.item0;
     const int nlisted = (int)jd.count[li];

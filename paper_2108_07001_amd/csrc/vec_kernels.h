@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void demap_vec(const DemapArgs a, const T* 
   constexpr bool T2 = !ML && sizeof(T) == 4;
   extern __shared__ double acc_lds[];  // [waves][S][4], then (T2) flagged counts [waves][S]
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
   const int waves = blockDim.x >> 6;
   const int S = a.S;
   unsigned int* nflag_lds = reinterpret_cast<unsigned int*>(acc_lds + waves * S * 4);
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void demap_vec_t2(const DemapArgs a, const 
   constexpr int NL = kMaxBits - LG;
   extern __shared__ double acc_lds[];  // [waves][S][4]
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
   const int waves = blockDim.x >> 6;
   const int S = a.S;
   // the SNR runs in the tile sequence: lane s holds run s's padded start and
