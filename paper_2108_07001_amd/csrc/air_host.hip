@@ -414,8 +414,9 @@ air_status run(air_ctx* ctx, const air_const* c, const void* in, const uint32_t*
     const int64_t npairs = (ntiles + 1) / 2;
     const int64_t stride = (int64_t)grid * kBlock;
     const int64_t tpw = mfma ? 2 * ((npairs + waves - 1) / waves) : 2 * ((N + stride - 1) / stride);
-    // tile indices and per-SNR sample counts of the second tier are 32-bit
-    if (N >= ((int64_t)1 << 32)) return fail(ctx, AIR_E_UNSUPPORTED, "N too large for one call");
+    // tile indices, sample indices (with the padding of the last tile pair)
+    // and per-SNR sample counts of the two tiers are 32-bit
+    if (N > ((int64_t)1 << 32) - 128) return fail(ctx, AIR_E_UNSUPPORTED, "N too large for one call");
     if (scratch) {
       // per SNR point of a launch: list slots (8 bytes), flagged counts per
       // wave (4) and 32 gathered sample indices per slot (4 each); three

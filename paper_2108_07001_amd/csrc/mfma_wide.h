@@ -18,6 +18,8 @@
 // of a sample is in the same frame 2^(a_j + S + c|y|^2) with
 // S + c|y|^2 <= K: no overflow, and the frame cancels in every output.
 #pragma once
+#include <type_traits>
+
 #include "mfma_kernels.h"
 
 namespace air {
@@ -283,9 +285,9 @@ template <int D>
 struct RawInput {
   uint32_t t;
   float z[D];
-  __device__ __forceinline__ void fetch(const SampleParams& p, int64_t st, int j) {
-    // 32-bit sample indices: a call holds fewer than 2^32 samples
-    const uint32_t n = (uint32_t)st * 32u + (uint32_t)j;
+  __device__ __forceinline__ void fetch(const SampleParams& p, uint32_t st, int j) {
+    // 32-bit sample indices: a call holds fewer than 2^32 - 128 samples
+    const uint32_t n = st * 32u + (uint32_t)j;
     const uint32_t nlast = (uint32_t)p.N - 1u;
     const uint32_t nc = n < nlast ? n : nlast;
     const uint32_t* __restrict__ txp = p.tx ? p.tx : reinterpret_cast<const uint32_t*>(p.in);
@@ -299,16 +301,16 @@ struct RawInput {
 // One group's sample for this lane's column j: validity, label and y.
 template <int D>
 struct WideSample {
-  int64_t n;
+  uint32_t n;      // 32-bit sample index (a call holds fewer than 2^32 - 128 samples)
   bool valid, live;
   int tl;          // label of the transmitted point (-1 none, -2 invalid index)
   int tq;          // an in-bounds label for record reads
   float y[D];
   template <bool BF>
-  __device__ __forceinline__ void setup(const SampleParams& p, const Tables<BF>& tb, int64_t st, int j,
+  __device__ __forceinline__ void setup(const SampleParams& p, const Tables<BF>& tb, uint32_t st, int j,
                                         bool flag_errors, const RawInput<D>& ri) {
-    n = st * 32 + j;
-    valid = n < p.N;
+    n = st * 32u + (uint32_t)j;
+    valid = n < (uint32_t)p.N;
     // table reads at an in-bounds index, unconditionally (selected afterwards),
     // so that no lane-dependent branch surrounds them
     const bool inb = ri.t < (uint32_t)p.M;
@@ -453,10 +455,14 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
   const int ntb = MB ? LV : m - 5;
   const float thr = Real<float>::starve(m);
   float* __restrict__ llr = static_cast<float*>(a.llr);
-  const int64_t ntiles = (a.N + 31) >> 5;
-  const int64_t npairs = (ntiles + 1) >> 1;
-  const int64_t wstride = (int64_t)gridDim.x * waves;
-  const int64_t wgid = (int64_t)blockIdx.x * waves + wave;
+  // exact-size forms: 32-bit pair and wave indices (fewer than 2^26 pairs,
+  // 2^16 waves), so that the round loop's counters and compares stay on the
+  // scalar unit (-1.9 % per 8-PSK^2 launch); the run-time-M forms, whose
+  // rounds are long, measured 2.6 % slower with them and keep 64-bit ones
+  typedef typename std::conditional<MB != 0, int, int64_t>::type QI;
+  const QI npairs = (QI)((((a.N + 31) >> 5) + 1) >> 1);
+  const QI wstride = (QI)gridDim.x * waves;
+  const QI wgid = (QI)blockIdx.x * waves + wave;
   const bool hj = (j >> 2) & 1;           // lane half holding row j of a tile
 
   // Per SNR point the waves take the pairs q0, q0 + wstride, ... with q0 =
@@ -467,7 +473,7 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
   // multiples of 32 waves (8 blocks) keeps each pair on the same XCD
   // (blocks are dealt to the 8 XCDs in turn), whose L2 still holds its
   // inputs from the previous SNR point.
-  const int64_t rem = npairs % wstride;
+  const QI rem = npairs % wstride;
   for (int s = 0; s < S; ++s) {
     double au = 0.0, av = 0.0, auu = 0.0, avv = 0.0;
     unsigned long long* slots = a.t2_list + ((int64_t)s * wstride + wgid) * a.t2_tpw;
@@ -477,7 +483,7 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
     // |y|^2 below which the half-precision operands are in range (see
     // WideOperand::build); none at all if c itself is out of range
     const float yy_lim = sp.c < 60000.0f ? __builtin_fminf(59000.0f, 9.0e8f / sp.c) / sp.c : -1.0f;
-    const int64_t q0 = (wgid + ((((int64_t)s * rem) % wstride) & ~(int64_t)31)) % wstride;
+    const QI q0 = (wgid + ((((QI)s * rem) % wstride) & ~(QI)31)) % wstride;
     // OWN: each lane sets up its own sample only (group A, tile 2 q, in
     // lanes 0..31; group B, tile 2 q + 1, in lanes 32..63) and forms both K
     // halves of its operand (build_pair); otherwise every lane sets up both
@@ -491,10 +497,10 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
         inB.fetch(sp, 2 * q0 + 1, j);
       }
     }
-    int64_t q = q0;
+    QI q = q0;
     for (; q < npairs; q += wstride) {
       WideSample<D> smA, smB;
-      const int64_t qn = q + wstride < npairs ? q + wstride : npairs - 1;
+      const QI qn = q + wstride < npairs ? q + wstride : npairs - 1;
       OP opA, opB;
       if constexpr (OWN) {
         smA.setup(sp, tb, 2 * q + h, j, s == 0, inA);
@@ -572,7 +578,7 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
         }
       }
       // own sample of this lane: group A in lanes 0..31, group B in 32..63
-      const int64_t n = sm.n;
+      const uint32_t n = sm.n;
       const bool valid = sm.valid;
       const bool live = sm.live;
       const int tl = sm.tl;
@@ -663,7 +669,7 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
         }
       }
 
-      float* lout = (llr && valid) ? llr + (int64_t)s * a.llr_stride_s + n * m : nullptr;
+      float* lout = (llr && valid) ? llr + (int64_t)s * a.llr_stride_s + (uint64_t)n * m : nullptr;
       if constexpr (ML) {
         (void)total;
         (void)thr;
@@ -757,13 +763,13 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
       // the rest of the wave's rounds at this SNR point: every live sample
       // (the lane's own one, sample tile 2 q + h) listed as it is
       for (; q < npairs; q += wstride) {
-        const int64_t n = (2 * q + h) * 32 + j;
-        const bool valid = n < sp.N;
+        const uint32_t n = (uint32_t)(2 * q + h) * 32u + (uint32_t)j;
+        const bool valid = n < (uint32_t)sp.N;
         const uint32_t t = (valid && sp.tx) ? sp.tx[n] : 0u;
         const bool bad = valid && sp.tx && !(t < (uint32_t)sp.M);
         if (s == 0 && bad) atomicOr(sp.err, 1);
         if (bad && llr)
-          for (int k = 0; k < m; ++k) llr[(int64_t)s * a.llr_stride_s + n * m + k] = Real<float>::nan();
+          for (int k = 0; k < m; ++k) llr[(int64_t)s * a.llr_stride_s + (uint64_t)n * m + k] = Real<float>::nan();
         const unsigned long long bm = __ballot(valid && !bad);
         const unsigned long long mlo = bm & 0xffffffffull, mhi = bm >> 32;
         nflag += __builtin_popcountll(bm);
