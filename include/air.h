@@ -122,7 +122,10 @@ int air_const_bits(const air_const *c);
 /* Soft demapping of a received block at one SNR.
  *  Y_dev:   N x D received points (double for AIR_FP64, else float).
  *  llr_dev: N x m LLRs in nats (double for AIR_FP64, else float).
- * N >= 1. */
+ * N >= 1. Calls in AIR_FP16X3 and AIR_BF16X3, and the exact (not max-log)
+ * calls in AIR_FP32, take at most 2^32 - 128 samples (32-bit sample indices)
+ * and return AIR_E_UNSUPPORTED beyond; this holds for every call below that
+ * takes N. */
 air_status air_llr(air_ctx *ctx, const air_const *c, const void *Y_dev, int64_t N,
                    double snr_db, air_prec prec, void *llr_dev);
 
