@@ -613,7 +613,7 @@ template <int D, bool BF, bool HALF>
 __device__ __forceinline__ void tier1_tile(const SampleTile<D, BF>& smp, const Tables<BF>& tb,
                                            bool has_tx, int j, int h, int m, int NT, int ntb,
                                            float thr, float* lout, float& u, float& v,
-                                           bool& need2) {
+                                           bool& need2, bool all_sides = true) {
   typedef typename MfmaOp<BF>::vec V;
   constexpr int NK = SampleTile<D, BF>::NK;
   constexpr int NE = HALF ? 8 : 16;
@@ -644,10 +644,18 @@ __device__ __forceinline__ void tier1_tile(const SampleTile<D, BF>& smp, const T
   float total;
   ts.combine(ntb, side, total);
 
+  // all_sides false (a job without LLRs, uniform): only the total and the
+  // transmitted point's sides count, as in the sweep's first tier
   bool starved = smp.ovf || !(total >= thr);
+  if (all_sides) {
 #pragma unroll
-  for (int i = 0; i < 2 * kMaxBits; ++i)
-    if (i < 2 * m) starved |= !(side[i] >= thr);
+    for (int i = 0; i < 2 * kMaxBits; ++i)
+      if (i < 2 * m) starved |= !(side[i] >= thr);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kMaxBits; ++k)
+      if (k < m) starved |= !((((smp.tl >> k) & 1) ? side[2 * k + 1] : side[2 * k]) >= thr);
+  }
   u = 0.f;
   v = 0.f;
   if (smp.live && !starved) {

@@ -704,11 +704,21 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
         continue;
       }
       // every sum is finite and >= 0 unless the operands left their range
-      // (ovf), so the smallest of them decides
+      // (ovf), so the smallest of them decides. Without LLRs (a uniform
+      // choice per call) only the sums that u and v use count: the total and
+      // the transmitted point's side of each bit; a starved other side adds
+      // less than 2^-200 of the total to it and enters nothing else (lanes
+      // without a transmitted label are not live then).
       float smin = total;
+      if (llr) {
 #pragma unroll
-      for (int i = 0; i < 2 * kMaxBits; ++i)
-        if (i < 2 * m) smin = __builtin_fminf(smin, side[i]);
+        for (int i = 0; i < 2 * kMaxBits; ++i)
+          if (i < 2 * m) smin = __builtin_fminf(smin, side[i]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < kMaxBits; ++k)
+          if (k < m) smin = __builtin_fminf(smin, bit_select(side[2 * k], side[2 * k + 1], tl, k));
+      }
       const bool starved = ovf || !(smin >= thr);
       float u = 0.f, v = -0.f;                 // -0 + x is x: no add for the first term
       if (live && !starved) {

@@ -111,7 +111,8 @@ __global__ __launch_bounds__(256) void serve_tier1(const JobDesc* __restrict__ j
       float u = 0.f, v = 0.f;
       bool need2;
       if (!direct) {
-        tier1_tile<D, BF, HALF>(smp, tb, jd.tx != nullptr, j, h, m, NT, ntb, thr, lout, u, v, need2);
+        tier1_tile<D, BF, HALF>(smp, tb, jd.tx != nullptr, j, h, m, NT, ntb, thr, lout, u, v, need2,
+                                jd.llr != nullptr || jd.tx == nullptr);
       } else {
         need2 = smp.live;
         if (smp.valid && !smp.live && lout && h == 0)

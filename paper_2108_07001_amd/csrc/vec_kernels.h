@@ -201,11 +201,21 @@ __global__ __launch_bounds__(kBlock) void demap_vec(const DemapArgs a, const T* 
             }
           if (tl >= 0) sv = (double)v;
         } else if constexpr (T2) {
-          // every sum is finite and >= 0 for finite inputs, so the smallest decides
+          // every sum is finite and >= 0 for finite inputs, so the smallest
+          // decides; without LLRs (a uniform choice per call) only the total
+          // and the transmitted point's sides count (the other sides enter
+          // nothing but the total; lanes without a transmitted label are not
+          // live then)
           T smin = total;
+          if (llr) {
 #pragma unroll
-          for (int i = 0; i < 2 * kMaxBits; ++i)
-            if (i < 2 * m) smin = __builtin_fminf(smin, side[i]);
+            for (int i = 0; i < 2 * kMaxBits; ++i)
+              if (i < 2 * m) smin = __builtin_fminf(smin, side[i]);
+          } else {
+#pragma unroll
+            for (int k = 0; k < kMaxBits; ++k)
+              if (k < m) smin = __builtin_fminf(smin, ((tl >> k) & 1) ? side[2 * k + 1] : side[2 * k]);
+          }
           need2 = !(smin >= Real<T>::starve(m));
           if (!need2) {
             T arg_t = 0;

@@ -84,9 +84,13 @@ def _halves_consistent(ctx, c, w, st_full, prec):
     h = N // 2
     parts = []
     for lo, hi in ((0, h), (h, N)):
-        st, _ = ctx.sweep(c, tx_dev(w.tx[lo:hi]), to_dev(np.ascontiguousarray(w.z[lo:hi]), torch.float32),
-                          w.snr_db, prec=prec)
+        # with LLRs, as the full call: which bit sides must stay inside the
+        # first tier's frame depends on whether LLRs are written
+        st, L = ctx.sweep(c, tx_dev(w.tx[lo:hi]), to_dev(np.ascontiguousarray(w.z[lo:hi]), torch.float32),
+                          w.snr_db, prec=prec, llr=True)
         parts.append((hi - lo, st.cpu().numpy()))
+        del L
+        torch.cuda.empty_cache()
     comb = sum(n * s[:, :2] for n, s in parts) / N
     np.testing.assert_allclose(st_full[:, :2], comb, rtol=0, atol=1e-7)
 

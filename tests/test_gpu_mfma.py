@@ -183,6 +183,30 @@ def test_direct_rounds_at_high_snr(ctx, prec):
     c.close()
 
 
+@pytest.mark.parametrize("prec", PRECS + ["fp32"])
+def test_mi_gmi_without_llrs(ctx, prec):
+    # Without LLRs only the total and the transmitted point's bit sides have
+    # to stay inside the first tier's frame: at 16..24 dB on 8-D, M = 2048
+    # most flagged items have only far sides starved, and they no longer go
+    # to the second tier. MI/GMI still match the oracle.
+    w = inputs.make("gauss8d2048", N=3000 + 37, snr_db=[16.0, 20.0, 24.0])
+    c = ctx.const(w.X, w.labels)
+    tx, z = tx_dev(w.tx), to_dev(w.z)
+    st_l, _ = ctx.sweep(c, tx, z, w.snr_db, prec=prec, llr=True)
+    ctx.sync()
+    rec_l = ctx.last_recomputed()
+    st, L = ctx.sweep(c, tx, z, w.snr_db, prec=prec)
+    ctx.sync()
+    rec = ctx.last_recomputed()
+    assert L is None
+    ref = oracle.sweep(w.X, w.labels, w.tx, w.z, w.snr_db, llr=False)
+    print(f"{prec}: second tier {rec} items without LLRs, {rec_l} with")
+    assert_stats(st.cpu().numpy(), ref["stats"], se_rel=2e-2)
+    assert_stats(st_l.cpu().numpy(), ref["stats"], se_rel=2e-2)
+    assert rec_l > 1000 and rec * 10 < rec_l
+    c.close()
+
+
 def test_call_words_start_clean(ctx):
     # the per-call words (tx-range error, second-tier counts) are zeroed by
     # the previous call's last kernel: counts and errors never carry over
@@ -192,7 +216,8 @@ def test_call_words_start_clean(ctx):
     z = to_dev(w.z)
 
     def run(wl, tx, sync=True):
-        st, _ = ctx.sweep(c, tx_dev(tx), z, wl.snr_db, prec="fp16x3")
+        # LLRs on: at 30 dB their far bit sides send items to the second tier
+        st, _ = ctx.sweep(c, tx_dev(tx), z, wl.snr_db, prec="fp16x3", llr=True)
         if sync:
             ctx.sync()
         return st.cpu().numpy(), ctx.last_recomputed(), ctx.last_exact()
@@ -205,7 +230,7 @@ def test_call_words_start_clean(ctx):
     assert a2[1:] == a[1:] and np.array_equal(a2[0], a[0])
     bad = w.tx.astype(np.int32).copy()
     bad[7] = 1 << 20
-    st, _ = ctx.sweep(c, tx_dev(bad), z, w.snr_db, prec="fp16x3")
+    st, _ = ctx.sweep(c, tx_dev(bad), z, w.snr_db, prec="fp16x3", llr=True)
     with pytest.raises(air.AirError):
         ctx.sync()
     assert np.isnan(st.cpu().numpy()).all()
