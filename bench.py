@@ -421,6 +421,21 @@ def large_sets(ctx, names, steps: int) -> dict:
                 f"{res[p]['second_tier_items']} items, exact {res[p]['exact_path_items']}")
         for p in ("fp16x3", "bf16x3"):
             res[p]["speedup_vs_fp32"] = res["fp32"]["ms_per_step"] / res[p]["ms_per_step"]
+        # the same sweep for MI/GMI alone (no LLRs written): only the total and
+        # the transmitted point's bit sides then need the first tier's frame
+        res["mi_gmi_only"] = {}
+        for p in ("fp16x3", "fp32"):
+            ctx.sweep(c, tx, z, w.snr_db, prec=p, stats_out=stats)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.sweep(c, tx, z, w.snr_db, prec=p, stats_out=stats)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            res["mi_gmi_only"][p] = {"ms_per_step": ms, "second_tier_items": int(ctx.last_recomputed()),
+                                     "sample_points_per_s": float(N) * S * M / (ms * 1e-3)}
+            log(f"{name} {p} MI/GMI only: {ms:.2f} ms/step, second tier {ctx.last_recomputed()} items")
+        res["mi_gmi_only"]["fp16x3"]["speedup_vs_fp32"] = (res["mi_gmi_only"]["fp32"]["ms_per_step"] /
+                                                           res["mi_gmi_only"]["fp16x3"]["ms_per_step"])
         out[name] = res
         del L, z, tx
         c.close()

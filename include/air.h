@@ -144,7 +144,11 @@ air_status air_mi_gmi(air_ctx *ctx, const air_const *c, const void *Y_dev,
  *  Z_dev:       N x D unit-variance noise (double for AIR_FP64, else float).
  *  snr_db_host: S SNR points in dB, S >= 1.
  *  stats_dev:   S x 4 doubles (MI, GMI, SE_MI, SE_GMI per SNR point).
- *  llr_dev:     S x N x m LLRs (nats), or NULL. */
+ *  llr_dev:     S x N x m LLRs (nats), or NULL.
+ * Without LLRs (here and in air_mi_gmi) only the bit sides that MI and GMI use
+ * must stay inside the FP32 frame, so at high SNR far fewer items need the
+ * second tier; the statistics agree with those of the same call with LLRs to
+ * FP32 rounding, not bit for bit. */
 air_status air_sweep(air_ctx *ctx, const air_const *c, const uint32_t *tx_dev,
                      const void *Z_dev, int64_t N, const double *snr_db_host, int S,
                      air_prec prec, double *stats_dev, void *llr_dev);
