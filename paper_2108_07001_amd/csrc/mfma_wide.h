@@ -706,9 +706,10 @@ __global__ __launch_bounds__(256, (MB && D <= 4) ? 3 : (D <= 12 ? 2 : 1)) void d
       // every sum is finite and >= 0 unless the operands left their range
       // (ovf), so the smallest of them decides. Without LLRs (a uniform
       // choice per call) only the sums that u and v use count: the total and
-      // the transmitted point's side of each bit; a starved other side adds
-      // less than 2^-200 of the total to it and enters nothing else (lanes
-      // without a transmitted label are not live then).
+      // the transmitted point's side of each bit. A starved other side enters
+      // nothing but the total, which its own bound keeps within 2^-20 of its
+      // value (at most M terms below the FP32 range, each under 2^-20 / M of
+      // the bound); lanes without a transmitted label are not live then.
       float smin = total;
       if (llr) {
 #pragma unroll
